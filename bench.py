@@ -1,0 +1,191 @@
+"""Throughput of the receive pipeline (delay-and-sum -> envelope -> log compression -> scan
+conversion) on one MI355X.
+
+Default workload: 128-element linear array, 256 scanlines from 64 focused transmits with 4
+receive lines each, 4096 int16 samples per channel at 40 MHz, 2048 output samples per line,
+512 x 512 B-mode image per frame, batches of 32 frames.  One step = one batch through the whole
+path.  Inputs are synthetic phantoms (20 points + 5000 speckle scatterers, 40 dB SNR) already
+resident in HBM when the timed region starts.
+
+Prints one JSON line (see the design doc for the fields).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "pixel·channel samples/s and frames(volumes)/s for DAS→B-mode; learned vs MV at stated error"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(name, per_launch_units):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it still matches
+    the kernel source; otherwise None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f).get(name)
+    if not d or d.get("source_hash") != kernel_hash(d.get("sources", [])):
+        return None
+    if d.get("units") != per_launch_units:
+        return None
+    return d.get("bytes_per_launch")
+
+
+def make_batch(g, n_frames, n_unique, device):
+    import torch
+    import synth
+    frames = []
+    for f in range(n_unique):
+        pos, amp, _ = synth.phantom.phantom_2d(g, 5000 + f)
+        frames.append(synth.rfsim.simulate_frame(g, pos, amp, 5000 + f, device=device))
+    idx = torch.arange(n_frames) % n_unique
+    return torch.stack(frames)[idx].contiguous()
+
+
+def cpu_baseline(g, rf_host, budget_s):
+    """The oracle, as it stands, on a bounded sample of the same batch (whole frames)."""
+    import oracle
+    t0 = time.perf_counter()
+    n = 0
+    while n < rf_host.shape[0]:
+        y = oracle.das(g, rf_host[n:n + 1])
+        oracle.bmode_2d(y[0], g.scan, 50.0)
+        n += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    pcs = n * g.n_lines * g.n_depth * g.n_el
+    return {"value": pcs / dt, "unit": "pixel·channel samples/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{n} frame(s) of the batch through the float64 oracle (DAS + envelope + log + scan "
+                      f"conversion), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--frames", type=int, default=32)
+    ap.add_argument("--unique-frames", type=int, default=8)
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this library runs on one GPU; multi-GPU runs are not part of it "
+                                   f"(asked for --gpus {args.gpus})"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1711_06127_amd as u
+    import synth
+
+    dev = torch.device("cuda:0")
+    u.lib()
+    g = synth.config_multiline_2d()
+    F = args.frames
+    t = time.perf_counter()
+    rf = make_batch(g, F, min(args.unique_frames, F), dev)
+    torch.cuda.synchronize()
+    log(f"inputs: {tuple(rf.shape)} int16 ({rf.numel() * 2 / 2**30:.2f} GiB) generated in {time.perf_counter() - t:.1f} s")
+    dg = u.DeviceGeometry(g, dev)
+    ws = u.BmodeWorkspace(dg, F)
+    lines = ws.lines(dg)
+    row_max = torch.empty((F, g.n_lines), dtype=torch.float32, device=dev)
+    img = torch.empty((F, *dg.scan_shape), dtype=torch.float32, device=dev)
+    ls_ws = torch.empty(4096, dtype=torch.uint8, device=dev)
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record()
+        u.beamform(rf, dg, out=lines)
+        if ev is not None:
+            ev[1].record()
+        u.envelope(lines, out=lines, row_max=row_max)
+        if ev is not None:
+            ev[2].record()
+        u.log_scan_convert(lines, dg, 50.0, row_max=row_max, out=img)
+        if ev is not None:
+            ev[3].record()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    das_ms = np.array([e[0].elapsed_time(e[1]) for e in evs])
+    env_ms = np.array([e[1].elapsed_time(e[2]) for e in evs])
+    scan_ms = np.array([e[2].elapsed_time(e[3]) for e in evs])
+    step_ms = wall * 1e3 / args.steps
+
+    # the whole-pipeline entry point gives the same image
+    ref = u.bmode(rf, dg, 50.0, ws=u.BmodeWorkspace(dg, F))
+    torch.cuda.synchronize()
+    same = bool(torch.equal(ref, img))
+
+    pcs = F * g.n_lines * g.n_depth * g.n_el
+    rf_bytes = rf.numel() * 2
+    out_bytes = F * g.n_lines * g.n_depth * 4
+    das_s = float(das_ms.mean()) * 1e-3
+    achieved = (rf_bytes + out_bytes) / das_s / 1e9
+    result = {
+        "metric": METRIC,
+        "value": pcs / (step_ms * 1e-3),
+        "unit": "pixel·channel samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "linear 128 el, 64 tx x 4 receive lines, 4096 int16 samples @ 40 MHz, "
+                               "256 x 2048 lines -> 512 x 512 B-mode", "frames_per_batch": F,
+                   "unique_frames": min(args.unique_frames, F), "dyn_range_db": 50},
+        "frames_per_s": F / (step_ms * 1e-3),
+        "stage_ms": {"das": float(das_ms.mean()), "envelope": float(env_ms.mean()),
+                     "log_scan": float(scan_ms.mean())},
+        "bmode_entry_matches": same,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic_from_profile("das", F), "kernel": "das (delay-and-sum)",
+                     "algorithmic_bytes": rf_bytes + out_bytes},
+    }
+    if not args.no_cpu:
+        rf_h = rf.cpu().numpy()
+        result["cpu_baseline"] = cpu_baseline(g, rf_h, args.cpu_budget)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

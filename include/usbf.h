@@ -1,0 +1,253 @@
+/*
+ * usbf -- ultrasound receive pipeline on AMD Instinct MI355X (gfx950).
+ *
+ * The receive chain of a software-defined ultrasound system (Goebl, Navab, Hennersperger,
+ * "SUPRA: open source software defined ultrasound processing for real-time applications",
+ * arXiv:1711.06127): receive beamforming by delay and sum, envelope detection, log
+ * compression and scan conversion (Sec. 1 pipeline list; Sec. 2 method list items 1-5),
+ * for 2D linear and 3D matrix probes.
+ *
+ * Conventions for every entry point below
+ *  - Array arguments are DEVICE pointers, owned by the caller, contiguous, row-major, and
+ *    must stay valid until the work enqueued on `stream` has finished.  Struct arguments
+ *    are HOST pointers read during the call only.  Nothing is retained after a call returns.
+ *  - Every call is asynchronous on `stream` (a HIP stream, 0 = the null stream) and never
+ *    synchronises the host.  Device faults surface at the caller's next synchronisation.
+ *  - Arguments are validated before anything is enqueued; on any error nothing is enqueued
+ *    and the outputs are untouched.  Return values: USBF_OK or a negative USBF_E* code;
+ *    usbf_status_string() gives the text, usbf_last_error_detail() the reason of the
+ *    calling thread's last failure.
+ *  - Stateless calls are reentrant: two beamformers with different parameters may read the
+ *    same channel data concurrently (the paper runs two differently parametrised
+ *    beamformers on one input, Sec. 2).
+ *  - Lengths in metres, times in seconds, all floating-point parameters binary32.
+ */
+#ifndef USBF_H
+#define USBF_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define USBF_OK            0
+#define USBF_EINVAL       -1  /* null pointer or a parameter outside its valid range      */
+#define USBF_ESHAPE       -2  /* sizes inconsistent with each other                        */
+#define USBF_EUNSUPPORTED -3  /* valid request beyond what the kernels implement           */
+#define USBF_EWORKSPACE   -4  /* workspace missing or smaller than usbf_workspace_bytes()  */
+#define USBF_EDEVICE      -5  /* HIP launch or runtime error                               */
+
+#define USBF_WINDOW_RECT 0
+#define USBF_WINDOW_HANN 1
+
+#define USBF_MAX_ELEMENTS 1024
+#define USBF_MAX_FRAMES   65535
+
+/*
+ * Probe, transmit and scanline geometry (device arrays).
+ *   el_pos      [n_el][3]    element centres; the array lies in the plane z = 0.
+ *   tx_origin   [n_tx][3]    transmit beam origin;  tx_dir [n_tx][3] its direction (any
+ *                            length > 0, normalised inside);  tx_focus [n_tx] focal range > 0
+ *                            along tx_dir.  The focused wave is modelled as converging on,
+ *                            then diverging from, a virtual source at the focus.
+ *   line_origin [n_lines][3] scanline origin; line_dir [n_lines][3] its direction;
+ *   line_tx     [n_lines]    transmit whose echoes form the line (multi-line acquisition
+ *                            when several lines share one transmit, Sec. 2 method list item 1).
+ *   array_dims  1: linear array, receive aperture limited along x only;
+ *               2: matrix array, separable aperture along x and y.
+ * The receive aperture is centred on the line origin.
+ */
+typedef struct usbf_geometry {
+  int32_t n_el;
+  const float* el_pos;
+  int32_t n_tx;
+  const float* tx_origin;
+  const float* tx_dir;
+  const float* tx_focus;
+  int32_t n_lines;
+  const float* line_origin;
+  const float* line_dir;
+  const int32_t* line_tx;
+  int32_t array_dims;
+} usbf_geometry;
+
+/*
+ * Receive parameters.
+ *   c speed of sound (> 0), fs sampling rate (> 0), t0 time of sample 0 relative to the
+ *   transmit's virtual-source arrival reference.
+ *   n_samples S >= 2 samples per channel.
+ *   Output sample j of every line lies at depth r_j = (depth_start + depth_step * j) * c / (2 fs),
+ *   j = 0 .. n_depth-1 (depth_start >= 0, depth_step >= 1, n_depth >= 1).
+ *   f_number > 0: at depth r the aperture is r / f_number wide; window USBF_WINDOW_*.
+ */
+typedef struct usbf_rx {
+  float c, fs, t0;
+  int32_t n_samples;
+  int32_t depth_start, depth_step, n_depth;
+  float f_number;
+  int32_t window;
+} usbf_rx;
+
+/*
+ * Scan-conversion grid (Sec. 1 pipeline list, last step; Sec. 2 method list item 5).
+ *   kind 0: 2D, parallel vertical lines at x = line_u[k]; pixel (i, k) at
+ *           (x0 + i*hx, z0 + k*hz), line depth = z.
+ *   kind 1: 3D, steered lines with tangents (line_u[iu], line_v[iv]) of the angles in x and
+ *           y; line index = iv * n_u + iu; voxel (i, j, k) at (x0 + i hx, y0 + j hy, z0 + k hz)
+ *           maps to u = x/z, v = y/z, range sqrt((x x + y y) + z z).
+ *   kind 2: 2D sector, lines with tangents line_u from a common apex at the origin;
+ *           u = x/z, range sqrt(x x + z z).
+ *   line_u[n_u], line_v[n_v]: device arrays, strictly increasing.  Line samples are at range
+ *   r0 + n*dr, n = 0 .. n_depth-1.  Pixels outside the lines' hull get `fill`.
+ *   Output layout [nz][nx] (2D) or [nz][ny][nx] (3D).
+ */
+typedef struct usbf_scan {
+  int32_t kind;
+  int32_t nx, ny, nz;
+  float x0, hx, y0, hy, z0, hz;
+  const float* line_u;
+  const float* line_v;
+  int32_t n_u, n_v;
+  float r0, dr;
+  int32_t n_depth;
+  float fill;
+} usbf_scan;
+
+/* ---------------------------------------------------------------- the pipeline stages */
+
+/*
+ * Receive beamforming by delay and sum (Sec. 1 pipeline list, "receive beamforming";
+ * Sec. 2 method list items 1-2): for every frame f, line l and depth sample j,
+ *   out[f][l][j] = sum_e w_e s_e / sum_e w_e  over the elements e inside the aperture,
+ * where s_e is channel e of transmit line_tx[l] in frame f, linearly interpolated at the
+ * two-way travel time tau = fs (T_tx + |e - p| / c) - fs t0 (0 outside samples 0..S-1;
+ * such elements still count in the denominator), w_e the window over the aperture
+ * (Hann: 1/2 + 1/2 cos(2 pi u), u = offset / aperture width), and out = 0 where no element
+ * is inside the aperture.  The integer sample index floor(tau) and the aperture and
+ * record-bound decisions follow the binary32 delay rule documented with
+ * usbf_delay_index_map(); the sum accumulates in binary32.
+ *   rf   int16 [n_frames][n_tx][n_el][n_samples]
+ *   out  float [n_frames][n_lines][n_depth]
+ * 1 <= n_frames <= USBF_MAX_FRAMES, 1 <= n_el <= USBF_MAX_ELEMENTS.
+ * A line_tx entry outside [0, n_tx) yields a line of zeros.
+ */
+int usbf_beamform(const int16_t* rf, int32_t n_frames, const usbf_geometry* geom,
+                  const usbf_rx* rx, float* out, hipStream_t stream);
+
+/*
+ * Envelope detection (Sec. 1 pipeline list, "envelope detection"; the Hilbert-transform
+ * envelope of the PSF study, Sec. 4): for each of n_rows rows of length n,
+ *   env = | IDFT( H . DFT(in) ) |,  H[0] = 1, H[k] = 2 for 0 < k < n/2, H[n/2] = 1 (n even),
+ *   H[k] = 0 otherwise (circular, no padding).
+ *   in, env  float [n_rows][n]  (in == env allowed: in place)
+ *   row_max  float [n_rows] maximum of each env row, or NULL.
+ * n must be 2^a 3^b 5^c with 8 <= n <= 2048.
+ */
+int usbf_envelope(const float* in, int64_t n_rows, int32_t n, float* env, float* row_max,
+                  hipStream_t stream);
+
+/*
+ * Log compression to a display range (Sec. 1 pipeline list; Sec. 2 method list item 4):
+ *   out = clamp(1 + (20 / dyn_range_db) log10(env / ref), 0, 1),  out = 0 where env <= 0,
+ * with ref the given reference, or when ref <= 0 the maximum of each frame.
+ *   env, out float [n_frames][frame_len] (in place allowed).
+ *   ws: device workspace of at least usbf_workspace_bytes(USBF_OP_LOG_COMPRESS, n_frames, 0, 0)
+ *   bytes when ref <= 0 (may be NULL otherwise).
+ */
+int usbf_log_compress(const float* env, int32_t n_frames, int64_t frame_len, float dyn_range_db,
+                      float ref, float* out, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Scan conversion of line data onto a Cartesian grid (Sec. 1 pipeline list, last step;
+ * Sec. 2 method list item 5): bilinear (kind 0, 2) or trilinear (kind 1) interpolation in
+ * (line coordinate, range).  The integer cell indices follow the binary32 rule documented
+ * with usbf_scan_index_map().
+ *   in  float [n_frames][n_lines][scan->n_depth], n_lines = n_u (2D) or n_u * n_v (3D)
+ *   out float [n_frames][grid]
+ */
+int usbf_scan_convert(const float* in, int32_t n_frames, const usbf_scan* scan, float* out,
+                      hipStream_t stream);
+
+/*
+ * Log compression fused into scan conversion: out = scan_convert(log_compress(env)) with the
+ * same results as the two calls in sequence (the paper's order: envelope, log compression,
+ * scan conversion).  ref <= 0 uses each frame's maximum; if row_max (the envelope's
+ * per-row maxima, [n_frames][n_lines]) is given it supplies that maximum, otherwise it is
+ * computed.  ws as for usbf_log_compress.
+ */
+int usbf_log_scan_convert(const float* env, const float* row_max, int32_t n_frames,
+                          const usbf_scan* scan, float dyn_range_db, float ref, float* out,
+                          void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * The whole receive pipeline, channel data to display image: beamform -> envelope ->
+ * log compression (frame maximum reference) -> scan conversion.
+ *   rf     int16 [n_frames][n_tx][n_el][n_samples]
+ *   image  float [n_frames][grid]
+ *   ws     at least usbf_workspace_bytes(USBF_OP_BMODE, n_frames, n_lines, n_depth) bytes.
+ * scan->n_depth must equal rx->n_depth and the scan's line count must equal n_lines.
+ */
+int usbf_bmode(const int16_t* rf, int32_t n_frames, const usbf_geometry* geom, const usbf_rx* rx,
+               const usbf_scan* scan, float dyn_range_db, float* image, void* ws, size_t ws_bytes,
+               hipStream_t stream);
+
+#define USBF_OP_LOG_COMPRESS 1
+#define USBF_OP_LOG_SCAN     2
+#define USBF_OP_BMODE        3
+#define USBF_OP_MV           4
+#define USBF_OP_APODNET      5
+
+/* Workspace bytes needed by operation `op` for the given sizes (0 if none). */
+size_t usbf_workspace_bytes(int32_t op, int64_t n_frames, int64_t n_lines, int64_t n_depth);
+
+/* ---------------------------------------------------------------- index maps (exported for tests) */
+
+/*
+ * The binary32 delay rule used by every beamforming kernel, evaluated for all
+ * (line, depth, element): each operation one IEEE binary32 op rounded to nearest, sqrt and
+ * division correctly rounded, no fused multiply-add, sums left to right.
+ *   per line:  u_l = d_l / sqrt(d_l.d_l), u_t likewise;  D = o_l - o_t;  g = D.u_t;
+ *              cl = u_l.u_t;  k = cl - 1;  U = D - g u_t;  V = u_l - cl u_t;
+ *              same = (o_l, d_l) equal bit for bit to (o_t, d_t)
+ *   constants: h = c / (fs + fs),  K = fs / c,  T0 = fs t0,  F2 = f_number + f_number
+ *   per pixel: b = depth_start + depth_step j (integer);  r = (float)b * h
+ *              a = same ? 0 : g + r k;   L2 = same ? 0 : |U + r V|^2
+ *              m = a + (r - F);  den = sqrt(m m + L2) + |m|
+ *              dtx = den > 0 ? a + (m >= 0 ? L2 : -L2) / den : a
+ *   per element: x = e - o_l;  A = x.x;  B = x.u_l;  q = A - (r + r) B
+ *              X = q + r r (0 if not > 0);  s = sqrt(X) + r;  drx = s > 0 ? q / s : 0
+ *              dt = K (dtx + drx) - T0;  i0 = b + floor(dt);  phi = dt - floor(dt)
+ *              active: F2 |x.x| <= r  (and F2 |x.y| <= r for matrix arrays)
+ *              valid:  0 <= i0 <= S - 2
+ * This is the exact travel time rearranged so that the large, exact part 2 r fs / c = b
+ * never enters floating point.
+ *   i0    int32 [n_lines][n_depth][n_el];  flags uint8 same shape, bit0 active, bit1 valid;
+ *   phi   float same shape, or NULL.
+ */
+int usbf_delay_index_map(const usbf_geometry* geom, const usbf_rx* rx, int32_t* i0, uint8_t* flags,
+                         float* phi, hipStream_t stream);
+
+/*
+ * The binary32 cell-index rule of the scan converter, per output pixel:
+ *   x = x0 + (float)i * hx  (likewise y, z; separate multiply and add);
+ *   kind 0: u = x, range = z;  kind 2: u = x / z, range = sqrt(x x + z z);
+ *   kind 1: u = x / z, v = y / z, range = sqrt((x x + y y) + z z);  (kinds 1, 2 need z > 0)
+ *   q = (range - r0) / dr;  iu = largest index with line_u[iu] <= u, capped at n_u - 2
+ *   (iv likewise);  jd = floor(q) capped at n_depth - 2;
+ *   inside iff line_u[0] <= u <= line_u[n_u-1] (likewise v) and 0 <= q <= n_depth - 1.
+ *   base int32 [grid]: (line index of the lower corner) * n_depth + jd, or -1 outside.
+ */
+int usbf_scan_index_map(const usbf_scan* scan, int32_t* base, hipStream_t stream);
+
+/* ---------------------------------------------------------------- status */
+const char* usbf_status_string(int status);
+const char* usbf_last_error_detail(void);
+const char* usbf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* USBF_H */

@@ -1,0 +1,264 @@
+"""Python binding of libusbf, the MI355X receive-pipeline library (include/usbf.h).
+
+Argument marshalling only: every step runs in the library's HIP kernels.  PyTorch supplies
+device memory and the current stream.  There is no CPU fallback: when libusbf.so is not
+built, or no GPU is present, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libusbf.so")
+
+OK, EINVAL, ESHAPE, EUNSUPPORTED, EWORKSPACE, EDEVICE = 0, -1, -2, -3, -4, -5
+WINDOW_RECT, WINDOW_HANN = 0, 1
+OP_LOG_COMPRESS, OP_LOG_SCAN, OP_BMODE, OP_MV, OP_APODNET = 1, 2, 3, 4, 5
+
+P = ctypes.c_void_p
+I32, I64, F32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float
+
+
+class UsbfError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        super().__init__(f"usbf status {status}: {detail}")
+        self.status = status
+
+
+class CGeometry(ctypes.Structure):
+    _fields_ = [("n_el", I32), ("el_pos", P), ("n_tx", I32), ("tx_origin", P), ("tx_dir", P),
+                ("tx_focus", P), ("n_lines", I32), ("line_origin", P), ("line_dir", P),
+                ("line_tx", P), ("array_dims", I32)]
+
+
+class CRx(ctypes.Structure):
+    _fields_ = [("c", F32), ("fs", F32), ("t0", F32), ("n_samples", I32), ("depth_start", I32),
+                ("depth_step", I32), ("n_depth", I32), ("f_number", F32), ("window", I32)]
+
+
+class CScan(ctypes.Structure):
+    _fields_ = [("kind", I32), ("nx", I32), ("ny", I32), ("nz", I32), ("x0", F32), ("hx", F32),
+                ("y0", F32), ("hy", F32), ("z0", F32), ("hz", F32), ("line_u", P), ("line_v", P),
+                ("n_u", I32), ("n_v", I32), ("r0", F32), ("dr", F32), ("n_depth", I32), ("fill", F32)]
+
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "usbf_beamform": (I32, [P, I32, P, P, P, P]),
+    "usbf_envelope": (I32, [P, I64, I32, P, P, P]),
+    "usbf_log_compress": (I32, [P, I32, I64, F32, F32, P, P, ctypes.c_size_t, P]),
+    "usbf_scan_convert": (I32, [P, I32, P, P, P]),
+    "usbf_log_scan_convert": (I32, [P, P, I32, P, F32, F32, P, P, ctypes.c_size_t, P]),
+    "usbf_bmode": (I32, [P, I32, P, P, P, F32, P, P, ctypes.c_size_t, P]),
+    "usbf_workspace_bytes": (ctypes.c_size_t, [I32, I64, I64, I64]),
+    "usbf_delay_index_map": (I32, [P, P, P, P, P, P]),
+    "usbf_scan_index_map": (I32, [P, P, P]),
+    "usbf_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "usbf_last_error_detail": (ctypes.c_char_p, []),
+    "usbf_version": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded libusbf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "or python paper_1711_06127_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _check(status: int):
+    if status != OK:
+        detail = lib().usbf_last_error_detail().decode()
+        raise UsbfError(int(status), f"{lib().usbf_status_string(status).decode()}: {detail}")
+
+
+def _stream(dev: torch.device):
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _need_cuda(t: torch.Tensor, name: str, dtype=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class DeviceGeometry:
+    """Probe/scanline geometry, receive parameters and (optionally) a scan grid, uploaded to
+    the device once and reused by every call.  `g` is any object with the attributes of
+    synth.geometry.Geometry (el_pos, tx_origin, ..., scan)."""
+
+    def __init__(self, g, device="cuda"):
+        dev = torch.device(device)
+        f32 = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=dev)
+        self.device = dev
+        self.n_el, self.n_tx, self.n_lines = int(g.el_pos.shape[0]), int(g.tx_origin.shape[0]), int(g.line_origin.shape[0])
+        self.n_samples, self.n_depth = int(g.n_samples), int(g.n_depth)
+        self.el_pos, self.tx_origin, self.tx_dir = f32(g.el_pos), f32(g.tx_origin), f32(g.tx_dir)
+        self.tx_focus, self.line_origin, self.line_dir = f32(g.tx_focus), f32(g.line_origin), f32(g.line_dir)
+        self.line_tx = torch.as_tensor(np.ascontiguousarray(g.line_tx, dtype=np.int32), device=dev)
+        self.geom = CGeometry(self.n_el, self.el_pos.data_ptr(), self.n_tx, self.tx_origin.data_ptr(),
+                              self.tx_dir.data_ptr(), self.tx_focus.data_ptr(), self.n_lines,
+                              self.line_origin.data_ptr(), self.line_dir.data_ptr(), self.line_tx.data_ptr(),
+                              int(g.array_dims))
+        self.rx = CRx(g.c, g.fs, g.t0, g.n_samples, g.depth_start, g.depth_step, g.n_depth, g.f_number,
+                      int(g.window))
+        self.scan = None
+        s = getattr(g, "scan", None)
+        if s is not None:
+            self.set_scan(s)
+
+    def set_scan(self, s):
+        dev = self.device
+        self.line_u = torch.as_tensor(np.ascontiguousarray(s.line_u, dtype=np.float32), device=dev)
+        self.line_v = torch.as_tensor(np.ascontiguousarray(s.line_v, dtype=np.float32), device=dev)
+        self.scan = CScan(s.kind, s.nx, s.ny, s.nz, s.x0, s.hx, s.y0, s.hy, s.z0, s.hz,
+                          self.line_u.data_ptr(), self.line_v.data_ptr(), s.n_u, s.n_v, s.r0, s.dr,
+                          s.n_depth, s.fill)
+        self.scan_shape = tuple(s.out_shape)
+
+
+def workspace_bytes(op: int, n_frames: int, n_lines: int = 0, n_depth: int = 0) -> int:
+    return int(lib().usbf_workspace_bytes(op, n_frames, n_lines, n_depth))
+
+
+def _ws(nbytes: int, dev):
+    return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+
+
+def beamform(rf: torch.Tensor, dg: DeviceGeometry, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Delay-and-sum.  rf int16 [F, n_tx, n_el, S] (or [n_tx, n_el, S]) -> float32 [F, n_lines, n_depth]."""
+    _need_cuda(rf, "rf", torch.int16)
+    if rf.dim() == 3:
+        rf = rf.unsqueeze(0)
+    F = rf.shape[0]
+    if tuple(rf.shape[1:]) != (dg.n_tx, dg.n_el, dg.n_samples):
+        raise ValueError(f"rf shape {tuple(rf.shape)} does not match geometry")
+    if out is None:
+        out = torch.empty((F, dg.n_lines, dg.n_depth), dtype=torch.float32, device=rf.device)
+    _check(lib().usbf_beamform(_ptr(rf), F, ctypes.byref(dg.geom), ctypes.byref(dg.rx), _ptr(out), _stream(rf.device)))
+    return out
+
+
+def envelope(x: torch.Tensor, out: torch.Tensor | None = None, row_max=False):
+    """Analytic-signal magnitude along the last axis.  Returns env, or (env, per-row maxima)
+    when row_max is True or a preallocated float32 tensor of x.shape[:-1]."""
+    _need_cuda(x, "x", torch.float32)
+    n = x.shape[-1]
+    rows = x.numel() // n
+    if out is None:
+        out = torch.empty_like(x)
+    if isinstance(row_max, torch.Tensor):
+        _need_cuda(row_max, "row_max", torch.float32)
+        rm = row_max
+    else:
+        rm = torch.empty(x.shape[:-1], dtype=torch.float32, device=x.device) if row_max else None
+    _check(lib().usbf_envelope(_ptr(x), rows, n, _ptr(out), _ptr(rm), _stream(x.device)))
+    return (out, rm) if rm is not None else out
+
+
+def log_compress(env: torch.Tensor, dyn_range_db: float = 50.0, ref: float | None = None,
+                 out: torch.Tensor | None = None) -> torch.Tensor:
+    """Per-frame log compression to [0, 1]; env [F, ...]; ref None -> each frame's maximum."""
+    _need_cuda(env, "env", torch.float32)
+    F = env.shape[0]
+    if out is None:
+        out = torch.empty_like(env)
+    ws = _ws(workspace_bytes(OP_LOG_COMPRESS, F), env.device)
+    _check(lib().usbf_log_compress(_ptr(env), F, env.numel() // F, dyn_range_db, 0.0 if ref is None else ref,
+                                   _ptr(out), _ptr(ws), ws.numel(), _stream(env.device)))
+    return out
+
+
+def scan_convert(lines: torch.Tensor, dg: DeviceGeometry, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Bilinear/trilinear scan conversion; lines [F, n_lines, n_depth] -> [F, *grid]."""
+    _need_cuda(lines, "lines", torch.float32)
+    F = lines.shape[0]
+    if out is None:
+        out = torch.empty((F, *dg.scan_shape), dtype=torch.float32, device=lines.device)
+    _check(lib().usbf_scan_convert(_ptr(lines), F, ctypes.byref(dg.scan), _ptr(out), _stream(lines.device)))
+    return out
+
+
+def log_scan_convert(env: torch.Tensor, dg: DeviceGeometry, dyn_range_db: float = 50.0, ref: float | None = None,
+                     row_max: torch.Tensor | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
+    _need_cuda(env, "env", torch.float32)
+    F = env.shape[0]
+    if out is None:
+        out = torch.empty((F, *dg.scan_shape), dtype=torch.float32, device=env.device)
+    ws = _ws(workspace_bytes(OP_LOG_SCAN, F), env.device)
+    _check(lib().usbf_log_scan_convert(_ptr(env), _ptr(row_max), F, ctypes.byref(dg.scan), dyn_range_db,
+                                       0.0 if ref is None else ref, _ptr(out), _ptr(ws), ws.numel(),
+                                       _stream(env.device)))
+    return out
+
+
+class BmodeWorkspace:
+    """Reusable workspace for bmode() (keeps allocation out of timed loops)."""
+
+    def __init__(self, dg: DeviceGeometry, n_frames: int):
+        self.nbytes = workspace_bytes(OP_BMODE, n_frames, dg.n_lines, dg.n_depth)
+        self.buf = _ws(self.nbytes, dg.device)
+        self.n_frames = n_frames
+
+    def lines(self, dg: DeviceGeometry) -> torch.Tensor:
+        n = self.n_frames * dg.n_lines * dg.n_depth
+        return self.buf[: 4 * n].view(torch.float32).view(self.n_frames, dg.n_lines, dg.n_depth)
+
+
+def bmode(rf: torch.Tensor, dg: DeviceGeometry, dyn_range_db: float = 50.0, out: torch.Tensor | None = None,
+          ws: BmodeWorkspace | None = None) -> torch.Tensor:
+    """Channel data -> display image: beamform, envelope, log compression, scan conversion."""
+    _need_cuda(rf, "rf", torch.int16)
+    if rf.dim() == 3:
+        rf = rf.unsqueeze(0)
+    F = rf.shape[0]
+    if out is None:
+        out = torch.empty((F, *dg.scan_shape), dtype=torch.float32, device=rf.device)
+    if ws is None or ws.n_frames != F:
+        ws = BmodeWorkspace(dg, F)
+    _check(lib().usbf_bmode(_ptr(rf), F, ctypes.byref(dg.geom), ctypes.byref(dg.rx), ctypes.byref(dg.scan),
+                            dyn_range_db, _ptr(out), _ptr(ws.buf), ws.nbytes, _stream(rf.device)))
+    return out
+
+
+def delay_index_map(dg: DeviceGeometry, with_phi: bool = True):
+    """(i0 int32, flags uint8, phi float32) each [n_lines, n_depth, n_el]."""
+    shape = (dg.n_lines, dg.n_depth, dg.n_el)
+    i0 = torch.empty(shape, dtype=torch.int32, device=dg.device)
+    fl = torch.empty(shape, dtype=torch.uint8, device=dg.device)
+    phi = torch.empty(shape, dtype=torch.float32, device=dg.device) if with_phi else None
+    _check(lib().usbf_delay_index_map(ctypes.byref(dg.geom), ctypes.byref(dg.rx), _ptr(i0), _ptr(fl), _ptr(phi),
+                                      _stream(dg.device)))
+    return i0, fl, phi
+
+
+def scan_index_map(dg: DeviceGeometry) -> torch.Tensor:
+    base = torch.empty(dg.scan_shape, dtype=torch.int32, device=dg.device)
+    _check(lib().usbf_scan_index_map(ctypes.byref(dg.scan), _ptr(base), _stream(dg.device)))
+    return base

@@ -1,0 +1,60 @@
+// Internal helpers shared by the library's translation units: status handling,
+// argument checks and launch utilities.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/usbf.h"
+
+namespace usbf {
+
+// Records why the calling thread's last call failed; returns `status`.
+int fail(int status, const char* fmt, ...);
+// Checks the last launch on this thread; USBF_EDEVICE with the HIP message on error.
+int check_launch(const char* what);
+
+#define USBF_REQUIRE(cond, status, ...)       \
+  do {                                        \
+    if (!(cond)) return ::usbf::fail((status), __VA_ARGS__); \
+  } while (0)
+
+inline bool finite_pos(float v) { return v > 0.0f && v < 3.0e38f; }
+
+// Number of workgroups dispatched round-robin over the MI355X's accelerator dies (XCDs).
+constexpr int kNumXcd = 8;
+
+// Remaps a linear workgroup id so that consecutive logical tiles run on the same XCD
+// (each XCD has its own L2): hardware dispatches id i to XCD i % 8.
+__device__ inline uint32_t xcd_swizzle(uint32_t bid, uint32_t nblocks) {
+  uint32_t per = nblocks / kNumXcd;
+  uint32_t rem = nblocks % kNumXcd;
+  uint32_t xcd = bid % kNumXcd;
+  uint32_t idx = bid / kNumXcd;
+  // XCDs [0, rem) own per+1 logical tiles, the rest own per
+  uint32_t start = xcd * per + (xcd < rem ? xcd : rem);
+  return start + idx;
+}
+
+// Geometry in kernel-argument form (device pointers, sizes) plus the binary32 constants of
+// the delay rule, computed once on the host with the same IEEE operations the rule names.
+struct DasArgs {
+  const float* el_pos;
+  const float* tx_origin;
+  const float* tx_dir;
+  const float* tx_focus;
+  const float* line_origin;
+  const float* line_dir;
+  const int32_t* line_tx;
+  int32_t n_el, n_tx, n_lines, array_dims;
+  int32_t n_samples, depth_start, depth_step, n_depth;
+  float h, K, T0, F2, f_number;
+  int32_t window;
+};
+
+int make_das_args(const usbf_geometry* g, const usbf_rx* rx, DasArgs* a);
+
+}  // namespace usbf

@@ -1,0 +1,216 @@
+// Envelope detection (Sec. 1 pipeline list; Hilbert-transform envelope of the PSF study,
+// Sec. 4): env = |IDFT(H . DFT(y))| per row, H keeping DC (and Nyquist), doubling the
+// positive and removing the negative frequencies.
+//
+// One workgroup owns a row at a time (grid-stride over rows so the twiddle table is built
+// once per workgroup) and runs a mixed-radix (2, 3, 4, 5) self-sorting Stockham FFT in LDS.
+// The inverse transform is done as a forward transform of the conjugate: the magnitude of
+// conj(FFT(conj(X))) / n needs no final conjugation.
+#include "common.h"
+
+namespace usbf {
+
+constexpr int kEnvThreads = 256;
+constexpr int kMaxStages = 16;
+// three n-point complex buffers (two ping-pong, one twiddle table) must fit the 64 KiB LDS
+// a workgroup gets without opting in to more
+constexpr int kMaxEnvelopeLength = 2048;
+
+struct FftPlan {
+  int n;
+  int n_stages;
+  int radix[kMaxStages];
+};
+
+struct c32 {
+  float x, y;
+};
+
+__device__ inline c32 cadd(c32 a, c32 b) { return {a.x + b.x, a.y + b.y}; }
+__device__ inline c32 csub(c32 a, c32 b) { return {a.x - b.x, a.y - b.y}; }
+__device__ inline c32 cmul(c32 a, c32 b) {
+  return {__builtin_fmaf(a.x, b.x, -a.y * b.y), __builtin_fmaf(a.x, b.y, a.y * b.x)};
+}
+__device__ inline c32 cscale(c32 a, float s) { return {a.x * s, a.y * s}; }
+__device__ inline c32 mul_mi(c32 a) { return {a.y, -a.x}; }  // -i * a
+
+// In-register forward DFTs of size 2, 3, 4, 5 (kernel e^{-2 pi i m q / R}).
+__device__ inline void dft2(c32* v) {
+  c32 a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+__device__ inline void dft4(c32* v) {
+  c32 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+  c32 t2 = cadd(v[1], v[3]), t3 = mul_mi(csub(v[1], v[3]));
+  v[0] = cadd(t0, t2);
+  v[2] = csub(t0, t2);
+  v[1] = cadd(t1, t3);
+  v[3] = csub(t1, t3);
+}
+__device__ inline void dft3(c32* v) {
+  const float h = 0.86602540378443864676f;  // sqrt(3)/2
+  c32 s = cadd(v[1], v[2]);
+  c32 d = csub(v[1], v[2]);
+  c32 m = {v[0].x - 0.5f * s.x, v[0].y - 0.5f * s.y};
+  c32 jd = mul_mi(cscale(d, h));
+  v[0] = cadd(v[0], s);
+  v[1] = cadd(m, jd);
+  v[2] = csub(m, jd);
+}
+__device__ inline void dft5(c32* v) {
+  const float c1 = 0.30901699437494742410f, c2 = -0.80901699437494742410f;
+  const float s1 = 0.95105651629515357212f, s2 = 0.58778525229247312917f;
+  c32 a1 = cadd(v[1], v[4]), b1 = csub(v[1], v[4]);
+  c32 a2 = cadd(v[2], v[3]), b2 = csub(v[2], v[3]);
+  c32 x0 = v[0];
+  c32 p1 = {x0.x + c1 * a1.x + c2 * a2.x, x0.y + c1 * a1.y + c2 * a2.y};
+  c32 p2 = {x0.x + c2 * a1.x + c1 * a2.x, x0.y + c2 * a1.y + c1 * a2.y};
+  c32 q1 = mul_mi({s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y});
+  c32 q2 = mul_mi({s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y});
+  v[0] = {x0.x + a1.x + a2.x, x0.y + a1.y + a2.y};
+  v[1] = cadd(p1, q1);
+  v[4] = csub(p1, q1);
+  v[2] = cadd(p2, q2);
+  v[3] = csub(p2, q2);
+}
+
+template <int R>
+__device__ inline void stage(const c32* __restrict__ a, c32* __restrict__ b, const c32* __restrict__ tw, int n, int ns) {
+  const int m = n / R;
+  const int tw_step = n / (ns * R);
+  for (int j = threadIdx.x; j < m; j += kEnvThreads) {
+    c32 v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = a[j + r * m];
+    const int k = j % ns;
+#pragma unroll
+    for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[r * k * tw_step]);
+    if constexpr (R == 2) dft2(v);
+    if constexpr (R == 3) dft3(v);
+    if constexpr (R == 4) dft4(v);
+    if constexpr (R == 5) dft5(v);
+    const int o = (j / ns) * ns * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) b[o + r * ns] = v[r];
+  }
+}
+
+// Forward FFT of buf[0] (result in buf[0] or buf[1]); returns the buffer holding the result.
+__device__ inline int fft_lds(c32* buf0, c32* buf1, const c32* tw, const FftPlan& P) {
+  c32* a = buf0;
+  c32* b = buf1;
+  int ns = 1;
+  int cur = 0;
+  for (int s = 0; s < P.n_stages; ++s) {
+    const int R = P.radix[s];
+    if (R == 4)
+      stage<4>(a, b, tw, P.n, ns);
+    else if (R == 2)
+      stage<2>(a, b, tw, P.n, ns);
+    else if (R == 3)
+      stage<3>(a, b, tw, P.n, ns);
+    else
+      stage<5>(a, b, tw, P.n, ns);
+    __syncthreads();
+    c32* t = a;
+    a = b;
+    b = t;
+    cur ^= 1;
+    ns *= R;
+  }
+  return cur;
+}
+
+__global__ __launch_bounds__(kEnvThreads) void envelope_kernel(const float* in, int64_t n_rows, FftPlan P,
+                                                               float* env, float* __restrict__ row_max) {
+  extern __shared__ c32 lds[];
+  const int n = P.n;
+  c32* buf[2] = {lds, lds + n};
+  c32* tw = lds + 2 * n;
+  for (int k = threadIdx.x; k < n; k += kEnvThreads) {
+    float s, c;
+    sincospif(2.0f * float(k) / float(n), &s, &c);
+    tw[k] = {c, -s};
+  }
+  const int half = n / 2;
+  const bool even = (n % 2) == 0;
+  const float inv_n = 1.0f / float(n);
+  __shared__ float red[kEnvThreads / 64];
+  for (int64_t row = blockIdx.x; row < n_rows; row += gridDim.x) {
+    const float* x = in + row * n;
+    for (int k = threadIdx.x; k < n; k += kEnvThreads) buf[0][k] = {x[k], 0.0f};
+    __syncthreads();
+    int cur = fft_lds(buf[0], buf[1], tw, P);
+    // analytic-signal weights, then conjugate for the inverse-by-forward transform
+    c32* X = buf[cur];
+    for (int k = threadIdx.x; k < n; k += kEnvThreads) {
+      float hk;
+      if (k == 0 || (even && k == half))
+        hk = 1.0f;
+      else if (k < (n + 1) / 2)
+        hk = 2.0f;
+      else
+        hk = 0.0f;
+      c32 v = X[k];
+      X[k] = {v.x * hk, -v.y * hk};
+    }
+    __syncthreads();
+    int cur2 = fft_lds(X, buf[cur ^ 1], tw, P);
+    c32* Y = (cur2 == 0) ? X : buf[cur ^ 1];
+    float mx = 0.0f;
+    float* e = env + row * n;
+    for (int k = threadIdx.x; k < n; k += kEnvThreads) {
+      c32 v = Y[k];
+      float m = sqrtf(__builtin_fmaf(v.x, v.x, v.y * v.y)) * inv_n;
+      e[k] = m;
+      mx = fmaxf(mx, m);
+    }
+    if (row_max) {
+      for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+      if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    }
+    __syncthreads();
+    if (row_max && threadIdx.x == 0) {
+      float m = red[0];
+      for (int w = 1; w < kEnvThreads / 64; ++w) m = fmaxf(m, red[w]);
+      row_max[row] = m;
+    }
+  }
+}
+
+int make_fft_plan(int n, FftPlan* P) {
+  P->n = n;
+  P->n_stages = 0;
+  int m = n;
+  const int order[4] = {4, 2, 3, 5};
+  for (int R : order) {
+    while (m % R == 0) {
+      if (P->n_stages >= kMaxStages) return USBF_EUNSUPPORTED;
+      P->radix[P->n_stages++] = R;
+      m /= R;
+    }
+  }
+  return m == 1 ? USBF_OK : USBF_EUNSUPPORTED;
+}
+
+int envelope_enqueue(const float* in, int64_t n_rows, int n, float* env, float* row_max, hipStream_t s) {
+  FftPlan P;
+  USBF_REQUIRE(make_fft_plan(n, &P) == USBF_OK, USBF_EUNSUPPORTED, "envelope length %d is not 2^a 3^b 5^c", n);
+  const int64_t blocks = std::min<int64_t>(n_rows, 8192);
+  const size_t lds = size_t(3) * n * sizeof(c32);
+  hipLaunchKernelGGL(envelope_kernel, dim3(unsigned(blocks)), dim3(kEnvThreads), lds, s, in, n_rows, P, env,
+                     row_max);
+  return check_launch("envelope_kernel");
+}
+
+}  // namespace usbf
+
+extern "C" int usbf_envelope(const float* in, int64_t n_rows, int32_t n, float* env, float* row_max,
+                             hipStream_t stream) {
+  USBF_REQUIRE(in && env, USBF_EINVAL, "null in or env");
+  USBF_REQUIRE(n_rows >= 1, USBF_EINVAL, "n_rows must be >= 1");
+  USBF_REQUIRE(n >= 8 && n <= usbf::kMaxEnvelopeLength, USBF_EUNSUPPORTED, "envelope length %d outside 8..%d", n,
+               usbf::kMaxEnvelopeLength);
+  return usbf::envelope_enqueue(in, n_rows, n, env, row_max, stream);
+}

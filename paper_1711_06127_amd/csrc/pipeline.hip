@@ -1,0 +1,53 @@
+// The whole receive pipeline in one call, in the paper's stage order (Sec. 1 pipeline list):
+// delay-and-sum beamforming -> envelope detection -> log compression -> scan conversion.
+// Log compression is applied to the four (eight) corner samples inside the scan converter,
+// which gives exactly the result of compressing every line sample first.
+#include "common.h"
+
+namespace usbf {
+int beamform_enqueue(const int16_t* rf, int32_t n_frames, const DasArgs& a, float* out, hipStream_t s);
+int envelope_enqueue(const float* in, int64_t n_rows, int n, float* env, float* row_max, hipStream_t s);
+int frame_max_enqueue(const float* x, int n_frames, int64_t frame_len, float* ws, hipStream_t s);
+int validate_scan(const usbf_scan* s);
+}  // namespace usbf
+
+extern "C" int usbf_bmode(const int16_t* rf, int32_t n_frames, const usbf_geometry* geom, const usbf_rx* rx,
+                          const usbf_scan* scan, float dyn_range_db, float* image, void* ws, size_t ws_bytes,
+                          hipStream_t stream) {
+  using namespace usbf;
+  DasArgs a;
+  int st = make_das_args(geom, rx, &a);
+  if (st) return st;
+  USBF_REQUIRE(rf && image && scan, USBF_EINVAL, "null rf, image or scan");
+  USBF_REQUIRE(n_frames >= 1 && n_frames <= USBF_MAX_FRAMES, USBF_EINVAL, "n_frames out of range");
+  USBF_REQUIRE(finite_pos(dyn_range_db), USBF_EINVAL, "dyn_range_db must be finite and > 0");
+  USBF_REQUIRE(scan->n_depth == rx->n_depth, USBF_ESHAPE, "scan n_depth %d != rx n_depth %d", scan->n_depth,
+               rx->n_depth);
+  const int64_t scan_lines = int64_t(scan->n_u) * (scan->kind == 1 ? scan->n_v : 1);
+  USBF_REQUIRE(scan_lines == geom->n_lines, USBF_ESHAPE, "scan covers %lld lines, geometry has %d",
+               (long long)scan_lines, geom->n_lines);
+  const size_t need = usbf_workspace_bytes(USBF_OP_BMODE, n_frames, a.n_lines, a.n_depth);
+  USBF_REQUIRE(ws && ws_bytes >= need, USBF_EWORKSPACE, "bmode needs %zu workspace bytes", need);
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  char* w = static_cast<char*>(ws);
+  const int64_t rows = int64_t(n_frames) * a.n_lines;
+  float* lines = reinterpret_cast<float*>(w);
+  float* row_max = reinterpret_cast<float*>(w + al(size_t(rows) * a.n_depth * sizeof(float)));
+  float* frame_ws = reinterpret_cast<float*>(reinterpret_cast<char*>(row_max) + al(size_t(rows) * sizeof(float)));
+  // validate the envelope length and the scan grid before anything is enqueued
+  {
+    int m = a.n_depth;
+    for (int R : {2, 3, 5})
+      while (m % R == 0) m /= R;
+    USBF_REQUIRE(m == 1 && a.n_depth >= 8 && a.n_depth <= 2048, USBF_EUNSUPPORTED,
+                 "n_depth %d is not 2^a 3^b 5^c in 8..2048", a.n_depth);
+  }
+  st = validate_scan(scan);
+  if (st) return st;
+  st = beamform_enqueue(rf, n_frames, a, lines, stream);
+  if (st) return st;
+  st = envelope_enqueue(lines, rows, a.n_depth, lines, row_max, stream);
+  if (st) return st;
+  return usbf_log_scan_convert(lines, row_max, n_frames, scan, dyn_range_db, 0.0f, image, frame_ws,
+                               al(size_t(n_frames) * sizeof(float)), stream);
+}

@@ -58,7 +58,7 @@ class ScanGrid:
 
     @property
     def out_shape(self):
-        if self.kind == 0:
+        if self.kind != 1:
             return (self.nz, self.nx)
         return (self.nz, self.ny, self.nx)
 

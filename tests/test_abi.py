@@ -1,0 +1,141 @@
+"""The C-ABI library loads, exports every declared entry point, and rejects bad arguments with
+the documented status codes before touching the GPU (runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "usbf.h")
+
+
+@pytest.fixture(scope="module")
+def u():
+    import paper_1711_06127_amd as u
+    if not os.path.exists(u.LIB_PATH):
+        pytest.skip("libusbf.so not built")
+    u.lib()
+    return u
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(usbf_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported(u):
+    names = declared_functions()
+    assert len(names) >= 12
+    L = ctypes.CDLL(u.LIB_PATH)
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) <= set(u.exported_symbols()) | {"usbf_version"}
+
+
+def test_status_strings(u):
+    L = u.lib()
+    assert L.usbf_status_string(0) == b"ok"
+    assert L.usbf_status_string(-1) == b"invalid argument"
+    assert L.usbf_status_string(-4) == b"workspace too small"
+    assert b"gfx950" in L.usbf_version()
+
+
+FAKE = 0x10000  # never dereferenced: every call below fails validation first
+
+
+def geom(u, n_el=4, n_tx=2, n_lines=3, dims=1):
+    return u.CGeometry(n_el, FAKE, n_tx, FAKE, FAKE, FAKE, n_lines, FAKE, FAKE, FAKE, dims)
+
+
+def rx(u, **kw):
+    d = dict(c=1540.0, fs=40e6, t0=0.0, n_samples=64, depth_start=0, depth_step=2, n_depth=32,
+             f_number=1.0, window=1)
+    d.update(kw)
+    return u.CRx(**d)
+
+
+@pytest.mark.parametrize("change,status", [
+    (dict(c=0.0), -1), (dict(c=float("nan")), -1), (dict(fs=-1.0), -1), (dict(f_number=0.0), -1),
+    (dict(n_samples=1), -1), (dict(depth_step=0), -1), (dict(n_depth=0), -1), (dict(window=7), -1),
+    (dict(depth_start=-1), -1), (dict(depth_step=1 << 20, n_depth=100), -3),
+])
+def test_beamform_rejects_bad_receive_parameters(u, change, status):
+    g, r = geom(u), rx(u, **change)
+    assert u.lib().usbf_beamform(FAKE, 1, ctypes.byref(g), ctypes.byref(r), FAKE, None) == status
+    assert len(u.lib().usbf_last_error_detail()) > 0
+
+
+def test_beamform_rejects_bad_geometry_and_sizes(u):
+    L = u.lib()
+    r = rx(u)
+    assert L.usbf_beamform(FAKE, 1, ctypes.byref(geom(u, n_el=0)), ctypes.byref(r), FAKE, None) == -2
+    assert L.usbf_beamform(FAKE, 1, ctypes.byref(geom(u, n_el=2000)), ctypes.byref(r), FAKE, None) == -3
+    assert L.usbf_beamform(FAKE, 1, ctypes.byref(geom(u, dims=3)), ctypes.byref(r), FAKE, None) == -1
+    assert L.usbf_beamform(FAKE, 0, ctypes.byref(geom(u)), ctypes.byref(r), FAKE, None) == -1
+    assert L.usbf_beamform(None, 1, ctypes.byref(geom(u)), ctypes.byref(r), FAKE, None) == -1
+    assert L.usbf_beamform(FAKE, 1, None, ctypes.byref(r), FAKE, None) == -1
+    g = geom(u)
+    g.line_tx = None
+    assert L.usbf_beamform(FAKE, 1, ctypes.byref(g), ctypes.byref(r), FAKE, None) == -1
+
+
+def test_envelope_and_log_reject(u):
+    L = u.lib()
+    assert L.usbf_envelope(FAKE, 4, 4, FAKE, None, None) == -3            # too short
+    assert L.usbf_envelope(FAKE, 4, 7 * 11 * 8, FAKE, None, None) == -3   # 7 and 11 unsupported
+    assert L.usbf_envelope(FAKE, 4, 8192, FAKE, None, None) == -3          # too long
+    assert L.usbf_envelope(None, 4, 64, FAKE, None, None) == -1
+    assert L.usbf_envelope(FAKE, 0, 64, FAKE, None, None) == -1
+    assert L.usbf_log_compress(FAKE, 2, 100, 0.0, 1.0, FAKE, None, 0, None) == -1
+    assert L.usbf_log_compress(FAKE, 2, 100, 50.0, 0.0, FAKE, None, 0, None) == -4   # needs workspace
+    assert L.usbf_log_compress(FAKE, 2, 100, 50.0, 0.0, FAKE, FAKE, 4, None) == -4   # too small
+    assert L.usbf_log_compress(FAKE, 0, 100, 50.0, 1.0, FAKE, None, 0, None) == -1
+
+
+def scan(u, **kw):
+    d = dict(kind=0, nx=8, ny=1, nz=8, x0=0.0, hx=1.0, y0=0.0, hy=0.0, z0=0.0, hz=1.0, line_u=FAKE,
+             line_v=FAKE, n_u=4, n_v=1, r0=0.0, dr=1.0, n_depth=16, fill=0.0)
+    d.update(kw)
+    return u.CScan(**d)
+
+
+@pytest.mark.parametrize("change,status", [
+    (dict(kind=3), -1), (dict(line_u=None), -1), (dict(nx=0), -1), (dict(n_u=1), -2),
+    (dict(kind=1, n_v=1), -2), (dict(kind=1, line_v=None), -1), (dict(dr=0.0), -1), (dict(n_depth=1), -2),
+])
+def test_scan_rejects(u, change, status):
+    s = scan(u, **change)
+    assert u.lib().usbf_scan_convert(FAKE, 1, ctypes.byref(s), FAKE, None) == status
+    assert u.lib().usbf_scan_index_map(ctypes.byref(s), FAKE, None) == status
+
+
+def test_bmode_rejects_inconsistent_shapes(u):
+    L = u.lib()
+    g, r = geom(u, n_lines=4), rx(u)
+    s = scan(u, n_depth=32)
+    ws = u.lib().usbf_workspace_bytes(3, 1, 4, 32)
+    assert ws > 0
+    s_bad = scan(u, n_depth=31)
+    assert L.usbf_bmode(FAKE, 1, ctypes.byref(g), ctypes.byref(r), ctypes.byref(s_bad), 50.0, FAKE, FAKE, ws,
+                        None) == -2
+    g5 = geom(u, n_lines=5)
+    assert L.usbf_bmode(FAKE, 1, ctypes.byref(g5), ctypes.byref(r), ctypes.byref(s), 50.0, FAKE, FAKE, ws,
+                        None) == -2
+    assert L.usbf_bmode(FAKE, 1, ctypes.byref(g), ctypes.byref(r), ctypes.byref(s), 50.0, FAKE, FAKE, ws - 1,
+                        None) == -4
+    r7 = rx(u, n_depth=7 * 8, n_samples=200)
+    s7 = scan(u, n_depth=56)
+    ws7 = u.lib().usbf_workspace_bytes(3, 1, 4, 56)
+    assert L.usbf_bmode(FAKE, 1, ctypes.byref(g), ctypes.byref(r7), ctypes.byref(s7), 50.0, FAKE, FAKE, ws7,
+                        None) == -3
+
+
+def test_workspace_sizes(u):
+    L = u.lib()
+    assert L.usbf_workspace_bytes(1, 32, 0, 0) >= 32 * 4
+    b = L.usbf_workspace_bytes(3, 32, 256, 2048)
+    assert b >= 32 * 256 * 2048 * 4 + 32 * 256 * 4 + 32 * 4
+    assert L.usbf_workspace_bytes(99, 1, 1, 1) == 0

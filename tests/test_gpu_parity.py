@@ -1,0 +1,264 @@
+"""GPU library vs CPU oracle: index maps bit-exact, values within 1e-4 of float64.
+
+Accuracy measure for beamformed lines and envelopes: max |gpu - oracle| / max |oracle| per
+frame; for log-compressed and scan-converted images: max |gpu - oracle| on the [0, 1] scale.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def usbf():
+    import paper_1711_06127_amd as u
+    u.lib()
+    return u
+
+
+def rel_err(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def sim(g, seed, n_frames=1, device="cuda", **kw):
+    frames = []
+    for f in range(n_frames):
+        pos, amp, _ = synth.phantom.phantom_2d(g, seed + f, **kw)
+        frames.append(synth.rfsim.simulate_frame(g, pos, amp, seed + f, device=device))
+    return torch.stack(frames).contiguous()
+
+
+def sub_geometry_3d(n_lines=48, seed=0):
+    """Subset of the 3D workload's lines (and their transmits), all 1024 elements."""
+    g = synth.config_volume_3d()
+    rng = np.random.default_rng(seed)
+    sel = np.sort(rng.choice(g.n_lines, n_lines, replace=False))
+    g.line_origin = np.ascontiguousarray(g.line_origin[sel])
+    g.line_dir = np.ascontiguousarray(g.line_dir[sel])
+    g.tx_origin = np.ascontiguousarray(g.tx_origin[sel])
+    g.tx_dir = np.ascontiguousarray(g.tx_dir[sel])
+    g.tx_focus = np.ascontiguousarray(g.tx_focus[sel])
+    g.line_tx = np.arange(n_lines, dtype=np.int32)
+    g.scan = None
+    return g
+
+
+# ------------------------------------------------------------------ delay index map
+
+@pytest.mark.parametrize("cfg", ["small", "multiline", "volume_subset"])
+def test_delay_index_map_bit_exact(usbf, cfg):
+    g = {"small": synth.config_small_2d, "multiline": synth.config_multiline_2d,
+         "volume_subset": sub_geometry_3d}[cfg]()
+    dg = usbf.DeviceGeometry(g)
+    i0, fl, phi = usbf.delay_index_map(dg)
+    torch.cuda.synchronize()
+    oi0, ophi, oact, oval = oracle.tof32(g)
+    oi0 = oi0.reshape(g.n_lines, g.n_depth, g.n_el)
+    assert np.array_equal(i0.cpu().numpy(), oi0)
+    ofl = (oact.astype(np.uint8) | (oval.astype(np.uint8) << 1)).reshape(i0.shape)
+    assert np.array_equal(fl.cpu().numpy(), ofl)
+    assert np.array_equal(phi.cpu().numpy().view(np.uint32), ophi.reshape(i0.shape).view(np.uint32))
+
+
+# ------------------------------------------------------------------ beamforming
+
+def test_beamform_small_frame_matches_oracle(usbf):
+    g = synth.config_small_2d()
+    rf = sim(g, 1000)
+    dg = usbf.DeviceGeometry(g)
+    y = usbf.beamform(rf, dg)
+    torch.cuda.synchronize()
+    ref = oracle.das(g, rf.cpu().numpy())
+    assert rel_err(y.cpu().numpy(), ref) <= TOL
+
+
+@pytest.mark.parametrize("n_frames", [1, 3, 5, 33])
+def test_beamform_multiline_frames(usbf, n_frames):
+    """Frame blocking (1, 2, 4 ... 32 frames per pass plus a ragged remainder) on the multi-line
+    geometry; sampled pixels of every frame against the oracle."""
+    g = synth.config_multiline_2d()
+    base = sim(g, 2000, n_frames=min(n_frames, 3))
+    rf = base[torch.arange(n_frames) % base.shape[0]].clone()
+    rf[3:] = torch.roll(rf[3:], shifts=1, dims=-1)       # frames beyond the first three differ too
+    dg = usbf.DeviceGeometry(g)
+    y = usbf.beamform(rf, dg).cpu().numpy()
+    rng = np.random.default_rng(n_frames)
+    m = 4000
+    pix = np.stack([rng.integers(0, n_frames, m), rng.integers(0, g.n_lines, m), rng.integers(0, g.n_depth, m)], 1)
+    ref = oracle.das(g, rf.cpu().numpy(), pix)
+    got = y[pix[:, 0], pix[:, 1], pix[:, 2]]
+    assert rel_err(got, ref) <= TOL
+
+
+def test_beamform_volume_subset(usbf):
+    """3D matrix probe, steered lines, separable Hann: a subset of lines with all 1024 elements."""
+    g = sub_geometry_3d(n_lines=24, seed=3)
+    rng = np.random.default_rng(0)
+    rf = torch.as_tensor(rng.integers(-3000, 3000, size=(1, g.n_tx, g.n_el, g.n_samples), dtype=np.int16)).cuda()
+    dg = usbf.DeviceGeometry(g)
+    y = usbf.beamform(rf, dg)
+    torch.cuda.synchronize()
+    ref = oracle.das(g, rf.cpu().numpy())
+    assert rel_err(y.cpu().numpy(), ref) <= TOL
+
+
+def test_beamform_edge_cases(usbf):
+    """Ragged depth count, a transmit index out of range (zero line), a depth grid starting at
+    sample 0 (empty aperture except the element under the line), rectangular window, t0 != 0."""
+    g = synth.config_tiny(n_el=7, n_tx=3, lines_per_tx=3, n_samples=300, window=synth.RECT)
+    g.n_depth = 137
+    g.t0 = float(np.float32(3.0e-7))
+    g.line_tx = g.line_tx.copy()
+    g.line_tx[4] = 99
+    rng = np.random.default_rng(7)
+    rf = torch.as_tensor(rng.integers(-30000, 30000, size=(2, g.n_tx, g.n_el, g.n_samples), dtype=np.int16)).cuda()
+    dg = usbf.DeviceGeometry(g)
+    y = usbf.beamform(rf, dg).cpu().numpy()
+    assert np.all(y[:, 4] == 0.0)
+    ok = np.ones(g.n_lines, bool)
+    ok[4] = False
+    g2 = synth.config_tiny(n_el=7, n_tx=3, lines_per_tx=3, n_samples=300, window=synth.RECT)
+    g2.n_depth, g2.t0 = g.n_depth, g.t0
+    ref = oracle.das(g2, rf.cpu().numpy())
+    assert rel_err(y[:, ok], ref[:, ok]) <= TOL
+
+
+def test_beamform_deterministic(usbf):
+    g = synth.config_small_2d()
+    rf = sim(g, 1234)
+    dg = usbf.DeviceGeometry(g)
+    a = usbf.beamform(rf, dg).clone()
+    b = usbf.beamform(rf, dg)
+    assert torch.equal(a, b)
+
+
+# ------------------------------------------------------------------ envelope, log, scan
+
+@pytest.mark.parametrize("n", [8, 60, 1000, 1024, 1536, 2048])
+def test_envelope_matches_oracle(usbf, n):
+    rng = np.random.default_rng(n)
+    x = rng.standard_normal((37, n)).astype(np.float32)
+    env, rm = usbf.envelope(torch.as_tensor(x).cuda(), row_max=True)
+    ref = oracle.envelope(x.astype(np.float64))
+    assert rel_err(env.cpu().numpy(), ref) <= TOL
+    assert np.array_equal(rm.cpu().numpy(), env.cpu().numpy().max(1))
+
+
+def test_envelope_in_place(usbf):
+    x = torch.randn(16, 1024, device="cuda")
+    ref = usbf.envelope(x.clone())
+    usbf.envelope(x, out=x)
+    assert torch.equal(x, ref)
+
+
+def test_log_compress_matches_oracle(usbf):
+    rng = np.random.default_rng(3)
+    env = rng.rayleigh(1.0, (3, 4096)).astype(np.float32)
+    env[1] *= 1e-3
+    env[2, :10] = 0.0
+    got = usbf.log_compress(torch.as_tensor(env).cuda(), 50.0).cpu().numpy()
+    for f in range(3):
+        assert np.abs(got[f] - oracle.log_compress(env[f].astype(np.float64), 50.0)).max() <= TOL
+    got2 = usbf.log_compress(torch.as_tensor(env).cuda(), 40.0, ref=2.5).cpu().numpy()
+    assert np.abs(got2 - oracle.log_compress(env.astype(np.float64), 40.0, ref=2.5)).max() <= TOL
+
+
+@pytest.mark.parametrize("cfg", ["small", "multiline", "volume"])
+def test_scan_index_map_bit_exact(usbf, cfg):
+    g = {"small": synth.config_small_2d, "multiline": synth.config_multiline_2d,
+         "volume": synth.config_volume_3d}[cfg]()
+    dg = usbf.DeviceGeometry(g)
+    base = usbf.scan_index_map(dg).cpu().numpy()
+    s = g.scan
+    if s.kind == 1:
+        iu, iv, jd, ok, *_ = oracle.scan_index_3d(s)
+        want = np.where(ok, (iv * s.n_u + iu) * s.n_depth + jd, -1)
+    else:
+        iu, jd, ok, *_ = oracle.scan_index_2d(s)
+        want = np.where(ok, iu * s.n_depth + jd, -1)
+    assert np.array_equal(base, want)
+
+
+def test_sector_scan_index_and_values(usbf):
+    """2D sector (kind 2): lines fanning out from the origin, u = x/z."""
+    tan_u = np.tan(np.radians(np.linspace(-35, 35, 96))).astype(np.float32)
+    s = synth.geometry.ScanGrid(kind=2, nx=300, ny=1, nz=260, x0=-0.05, hx=1e-4 / 0.3 * 1.0, y0=0, hy=0,
+                                z0=0.0, hz=2e-4, line_u=tan_u, line_v=np.zeros(1, np.float32), r0=1e-3,
+                                dr=float(np.float32(5e-5)), n_depth=1000)
+    s.hx = float(np.float32(1e-1 / 299))
+    g = synth.config_small_2d()
+    dg = usbf.DeviceGeometry(g)
+    dg.set_scan(s)
+    base = usbf.scan_index_map(dg).cpu().numpy()
+    iu, jd, ok, *_ = oracle.scan_index_2d(s)
+    assert ok.sum() > 1000
+    assert np.array_equal(base, np.where(ok, iu * s.n_depth + jd, -1))
+    lines = np.random.default_rng(1).standard_normal((1, 96, 1000)).astype(np.float32)
+    got = usbf.scan_convert(torch.as_tensor(lines).cuda(), dg).cpu().numpy()[0]
+    ref = oracle.scan_convert_2d(lines[0].astype(np.float64), s)
+    assert np.abs(got - ref).max() <= TOL * np.abs(ref).max()
+
+
+def test_scan_convert_3d_matches_oracle(usbf):
+    g = synth.config_volume_3d()
+    s = g.scan
+    dg = usbf.DeviceGeometry(g)
+    rng = np.random.default_rng(5)
+    lines = rng.random((1, g.n_lines, g.n_depth)).astype(np.float32)
+    got = usbf.scan_convert(torch.as_tensor(lines).cuda(), dg).cpu().numpy()[0]
+    zs = [0, 1, 17, 64, 100, 127]
+    ref = oracle.scan_convert_3d(lines[0].astype(np.float64), s, z_slices=zs)
+    assert np.abs(got[zs] - ref).max() <= TOL
+
+
+def test_log_scan_fused_equals_sequence(usbf):
+    g = synth.config_small_2d()
+    dg = usbf.DeviceGeometry(g)
+    env = torch.rand(2, g.n_lines, g.n_depth, device="cuda") ** 4
+    seq = usbf.scan_convert(usbf.log_compress(env, 50.0), dg)
+    fused = usbf.log_scan_convert(env, dg, 50.0)
+    assert (seq - fused).abs().max().item() <= 1e-6
+
+
+# ------------------------------------------------------------------ whole pipeline
+
+def test_bmode_small_frame_end_to_end(usbf):
+    g = synth.config_small_2d()
+    rf = sim(g, 1000)
+    dg = usbf.DeviceGeometry(g)
+    img = usbf.bmode(rf, dg, 50.0).cpu().numpy()[0]
+    ref = oracle.bmode_2d(oracle.das(g, rf.cpu().numpy())[0], g.scan, 50.0)
+    assert np.abs(img - ref).max() <= TOL
+
+
+def test_bmode_multiline_frames_end_to_end(usbf):
+    g = synth.config_multiline_2d()
+    rf = sim(g, 2100, n_frames=2)
+    dg = usbf.DeviceGeometry(g)
+    img = usbf.bmode(rf, dg, 50.0).cpu().numpy()
+    bf = oracle.das(g, rf.cpu().numpy())
+    for f in range(2):
+        ref = oracle.bmode_2d(bf[f], g.scan, 50.0)
+        assert np.abs(img[f] - ref).max() <= TOL
+
+
+def test_point_targets_peak_on_their_pixels(usbf):
+    """Noiseless point targets on the pixel grid: the GPU envelope peaks on each target pixel
+    within its neighbourhood."""
+    g = synth.config_small_2d()
+    pp, pa, lj = synth.phantom.points_2d(g)
+    rf = synth.rfsim.simulate_frame(g, pp, pa, 0, noise=False, device="cuda").unsqueeze(0).contiguous()
+    dg = usbf.DeviceGeometry(g)
+    env = usbf.envelope(usbf.beamform(rf, dg))[0].cpu().numpy()
+    for (l, j) in lj:
+        win = env[max(l - 2, 0):l + 3, j - 20:j + 21]
+        ll, jj = np.unravel_index(np.argmax(win), win.shape)
+        assert (ll + max(l - 2, 0), jj + j - 20) == (l, j)
