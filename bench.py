@@ -52,13 +52,27 @@ def traffic_from_profile(name, per_launch_units):
     return d.get("bytes_per_launch")
 
 
-def make_batch(g, n_frames, n_unique, device):
+WORKLOADS = {
+    # name: (geometry builder, default frames per batch, description)
+    "multiline": ("config_multiline_2d", 32, "linear 128 el, 64 tx x 4 receive lines, 4096 int16 samples @ 40 MHz, "
+                                              "256 x 2048 lines -> 512 x 512 B-mode"),
+    "small": ("config_small_2d", 64, "linear 64 el, 64 tx x 1 line, 2048 int16 samples @ 40 MHz, "
+                                     "64 x 1024 lines -> 256 x 256 B-mode"),
+    "volume": ("config_volume_3d", 1, "matrix 32 x 32 el, 1024 steered tx/lines over +-30 deg, 2000 int16 samples "
+                                      "@ 20 MHz, 32 x 32 x 1000 lines -> 128^3 B-mode volume"),
+}
+
+
+def make_batch(g, n_frames, n_unique, device, volume=False):
     import torch
     import synth
     frames = []
     for f in range(n_unique):
-        pos, amp, _ = synth.phantom.phantom_2d(g, 5000 + f)
-        frames.append(synth.rfsim.simulate_frame(g, pos, amp, 5000 + f, device=device))
+        if volume:
+            frames.append(synth.rfsim.simulate_volume(g, 7000 + f, device=device))
+        else:
+            pos, amp, _ = synth.phantom.phantom_2d(g, 5000 + f)
+            frames.append(synth.rfsim.simulate_frame(g, pos, amp, 5000 + f, device=device))
     idx = torch.arange(n_frames) % n_unique
     return torch.stack(frames)[idx].contiguous()
 
@@ -70,7 +84,10 @@ def cpu_baseline(g, rf_host, budget_s):
     n = 0
     while n < rf_host.shape[0]:
         y = oracle.das(g, rf_host[n:n + 1])
-        oracle.bmode_2d(y[0], g.scan, 50.0)
+        if g.scan.kind == 1:
+            oracle.bmode_3d(y[0], g.scan, 50.0)
+        else:
+            oracle.bmode_2d(y[0], g.scan, 50.0)
         n += 1
         if time.perf_counter() - t0 >= budget_s:
             break
@@ -87,7 +104,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--frames", type=int, default=32)
+    ap.add_argument("--workload", default="multiline", choices=sorted(WORKLOADS))
+    ap.add_argument("--frames", type=int, default=0, help="frames per batch (0: workload default)")
     ap.add_argument("--unique-frames", type=int, default=8)
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -105,10 +123,11 @@ def main():
 
     dev = torch.device("cuda:0")
     u.lib()
-    g = synth.config_multiline_2d()
-    F = args.frames
+    builder, default_frames, desc = WORKLOADS[args.workload]
+    g = getattr(synth, builder)()
+    F = args.frames or default_frames
     t = time.perf_counter()
-    rf = make_batch(g, F, min(args.unique_frames, F), dev)
+    rf = make_batch(g, F, min(args.unique_frames, F), dev, volume=args.workload == "volume")
     torch.cuda.synchronize()
     log(f"inputs: {tuple(rf.shape)} int16 ({rf.numel() * 2 / 2**30:.2f} GiB) generated in {time.perf_counter() - t:.1f} s")
     dg = u.DeviceGeometry(g, dev)
@@ -169,8 +188,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "linear 128 el, 64 tx x 4 receive lines, 4096 int16 samples @ 40 MHz, "
-                               "256 x 2048 lines -> 512 x 512 B-mode", "frames_per_batch": F,
+        "config": {"workload": desc, "frames_per_batch": F,
                    "unique_frames": min(args.unique_frames, F), "dyn_range_db": 50},
         "frames_per_s": F / (step_ms * 1e-3),
         "stage_ms": {"das": float(das_ms.mean()), "envelope": float(env_ms.mean()),

@@ -58,6 +58,10 @@ extern "C" {
  *                            when several lines share one transmit, Sec. 2 method list item 1).
  *   array_dims  1: linear array, receive aperture limited along x only;
  *               2: matrix array, separable aperture along x and y.
+ *   lines_per_tx  work-grouping hint, no effect on results: G > 1 announces that each run of
+ *               G consecutive lines starting at a multiple of G shares one transmit, so the
+ *               channel data of that transmit is staged once for the G lines (G = 2, 4, 8 are
+ *               used; 0 or 1: no grouping).  A wrong hint only costs speed.
  * The receive aperture is centred on the line origin.
  */
 typedef struct usbf_geometry {
@@ -72,6 +76,7 @@ typedef struct usbf_geometry {
   const float* line_dir;
   const int32_t* line_tx;
   int32_t array_dims;
+  int32_t lines_per_tx;
 } usbf_geometry;
 
 /*

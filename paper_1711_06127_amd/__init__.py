@@ -32,7 +32,7 @@ class UsbfError(RuntimeError):
 class CGeometry(ctypes.Structure):
     _fields_ = [("n_el", I32), ("el_pos", P), ("n_tx", I32), ("tx_origin", P), ("tx_dir", P),
                 ("tx_focus", P), ("n_lines", I32), ("line_origin", P), ("line_dir", P),
-                ("line_tx", P), ("array_dims", I32)]
+                ("line_tx", P), ("array_dims", I32), ("lines_per_tx", I32)]
 
 
 class CRx(ctypes.Structure):
@@ -108,6 +108,16 @@ def _need_cuda(t: torch.Tensor, name: str, dtype=None):
         raise ValueError(f"{name} must be contiguous")
 
 
+def lines_per_tx_hint(line_tx) -> int:
+    """Largest G in (8, 4, 2) such that every run of G consecutive lines shares a transmit."""
+    lt = np.asarray(line_tx)
+    for G in (8, 4, 2):
+        n = (lt.size // G) * G
+        if n and np.all(lt[:n].reshape(-1, G) == lt[:n].reshape(-1, G)[:, :1]):
+            return G
+    return 1
+
+
 class DeviceGeometry:
     """Probe/scanline geometry, receive parameters and (optionally) a scan grid, uploaded to
     the device once and reused by every call.  `g` is any object with the attributes of
@@ -125,7 +135,7 @@ class DeviceGeometry:
         self.geom = CGeometry(self.n_el, self.el_pos.data_ptr(), self.n_tx, self.tx_origin.data_ptr(),
                               self.tx_dir.data_ptr(), self.tx_focus.data_ptr(), self.n_lines,
                               self.line_origin.data_ptr(), self.line_dir.data_ptr(), self.line_tx.data_ptr(),
-                              int(g.array_dims))
+                              int(g.array_dims), lines_per_tx_hint(g.line_tx))
         self.rx = CRx(g.c, g.fs, g.t0, g.n_samples, g.depth_start, g.depth_step, g.n_depth, g.f_number,
                       int(g.window))
         self.scan = None

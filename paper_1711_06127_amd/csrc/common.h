@@ -49,7 +49,7 @@ struct DasArgs {
   const float* line_origin;
   const float* line_dir;
   const int32_t* line_tx;
-  int32_t n_el, n_tx, n_lines, array_dims;
+  int32_t n_el, n_tx, n_lines, array_dims, lines_per_tx;
   int32_t n_samples, depth_start, depth_step, n_depth;
   float h, K, T0, F2, f_number;
   int32_t window;

@@ -1,81 +1,461 @@
 // Receive beamforming by delay and sum (Sec. 1 pipeline list, "receive beamforming";
 // Sec. 2 method list items 1-2) and the exported delay-index map.
 //
-// Work decomposition: one workgroup per (line, run of 256 depth samples); one lane per
-// output sample.  The per-(line, element) receive constants are staged once in LDS; every
-// lane evaluates the binary32 delay rule of its (pixel, element) pairs once and reuses the
-// tap for a block of FB frames, so the delay arithmetic is amortised over the batch while
-// each int16 channel sample is fetched once per frame.
+// Work decomposition.  A workgroup of 256 lanes owns a tile of G consecutive scanlines that
+// share one transmit (multi-line acquisition) times 256/G consecutive depth samples, one lane
+// per output sample, for a block of FB frames.  Elements are processed in chunks of up to 8:
+//   1. every lane evaluates the binary32 delay rule for its pixel and the chunk's elements
+//      once and keeps (LDS offset, (1-phi) w, phi w) in registers -- the delay arithmetic is
+//      thus shared by all FB frames;
+//   2. for each stage of FS frames the workgroup copies, with wide coalesced loads, the part
+//      of each element's int16 trace that the tile can touch (its window, known from the
+//      delays at the tile's first and last depth because the delay grows with depth) into
+//      LDS as binary32, frames innermost;
+//   3. every lane reads the two neighbouring samples of all FS frames with two 16-byte LDS
+//      reads and accumulates with two FMAs per frame.
+// A (pixel, element) pair whose samples fall outside the staged window (only for unusual
+// geometry) reads global memory directly, so the result never depends on the tiling.
+#include <climits>
+
 #include "common.h"
 #include "tof.h"
 
 namespace usbf {
 
 constexpr int kDasThreads = 256;
+constexpr int kMaxChunk = 8;
+constexpr int kWindowMargin = 32;     // samples beyond 2 * depths per line in a window
+constexpr int kBufferBytes = 24576;   // one staging buffer (two per workgroup)
 
-template <int FB>
-__global__ __launch_bounds__(kDasThreads) void das_gather_kernel(const int16_t* __restrict__ rf, int n_frames,
-                                                                 DasArgs a, float* __restrict__ out) {
-  extern __shared__ float4 s_el[];  // (A, B, dx, dy) per element for this workgroup's line
-  const int l = blockIdx.y;
-  const int j = blockIdx.x * kDasThreads + threadIdx.x;
-  LineGeom L;
-  line_geom(a, l, L);
-  for (int e = threadIdx.x; e < a.n_el; e += kDasThreads) {
-    ElemGeom E = elem_geom(a, L, e);
-    s_el[e] = make_float4(E.A, E.B, E.dx, E.dy);
+template <int FS>
+struct FVec;
+template <>
+struct FVec<1> {
+  using T = float;
+  __device__ static float get(const T& v, int) { return v; }
+  __device__ static void set(T& v, int, float x) { v = x; }
+};
+template <>
+struct FVec<2> {
+  using T = float2;
+  __device__ static float get(const T& v, int f) { return f == 0 ? v.x : v.y; }
+  __device__ static void set(T& v, int f, float x) { (f == 0 ? v.x : v.y) = x; }
+};
+template <>
+struct FVec<4> {
+  using T = float4;
+  __device__ static float get(const T& v, int f) { return f == 0 ? v.x : f == 1 ? v.y : f == 2 ? v.z : v.w; }
+  __device__ static void set(T& v, int f, float x) { (f == 0 ? v.x : f == 1 ? v.y : f == 2 ? v.z : v.w) = x; }
+};
+
+// Compile-time shape of a tile: G lines x TD depths; a window of SPAN samples per element for
+// depth_step <= 2; EC elements per chunk so that one staging buffer fits kBufferBytes; IPT
+// staging items (4 samples x FS frames) per lane.
+template <int G, int FS>
+struct Shape {
+  static constexpr int TD = kDasThreads / G;
+  static constexpr int SPAN = 2 * TD + kWindowMargin;
+  static constexpr int EC0 = kBufferBytes / (SPAN * FS * 4);
+  static constexpr int EC = EC0 < kMaxChunk ? (EC0 < 1 ? 1 : EC0) : kMaxChunk;
+  static constexpr int BUFV = EC * SPAN;  // staging buffer length in frame vectors
+  static constexpr int IPT = (EC * (SPAN / 4) + kDasThreads - 1) / kDasThreads;
+};
+
+struct TileArgs {
+  int span;      // staged samples per element (multiple of 4)
+  int ec;        // elements per chunk
+  int n_dtiles;  // depth tiles per line
+  int pshift;    // 1: windows split into even and odd samples (even depth_step), else 0
+};
+
+// LDS of one workgroup: two staging buffers, the per-(line, element) receive constants of the
+// G lines, their LineGeom, and per element the tap window [lo, hi] and flags.
+// A staged window holds the samples of one element for FS frames; with pshift = 1 it is split
+// into even and odd samples (sample i at index (i & 1) * span/2 + i/2): lanes on consecutive
+// depths read taps depth_step = 2 samples apart, so their reads are consecutive in LDS.
+template <int G, int FS>
+struct TileLds {
+  typename FVec<FS>::T* win;  // [2][BUFV]
+  float4* geo;                // [G][n_el]: (A, B, dx, dy)
+  LineGeom* lines;            // [G]
+  int2* wnd;                  // [n_el]: (lo, hi)
+  int* flg;                   // [n_el]: bit 0 needed, bit 1 staged
+};
+
+// two staging buffers plus one all-zero frame vector (kept zero for the whole kernel): taps
+// that contribute nothing read it, so the accumulation needs no branch
+template <int G, int FS>
+__host__ __device__ constexpr size_t window_bytes() {
+  return (2 * size_t(Shape<G, FS>::BUFV) + 1) * FS * sizeof(float);
+}
+
+template <int G, int FS>
+__host__ __device__ inline size_t tile_lds_bytes(int n_el) {
+  return window_bytes<G, FS>() + size_t(G) * n_el * sizeof(float4) + G * sizeof(LineGeom) +
+         size_t(n_el) * (sizeof(int2) + sizeof(int));
+}
+
+template <int G, int FS>
+__device__ inline TileLds<G, FS> carve(unsigned char* base, int n_el) {
+  using V = typename FVec<FS>::T;
+  TileLds<G, FS> t;
+  t.win = reinterpret_cast<V*>(base);
+  t.geo = reinterpret_cast<float4*>(base + window_bytes<G, FS>());
+  t.lines = reinterpret_cast<LineGeom*>(t.geo + size_t(G) * n_el);
+  t.wnd = reinterpret_cast<int2*>(t.lines + G);
+  t.flg = reinterpret_cast<int*>(t.wnd + n_el);
+  return t;
+}
+
+__device__ inline int32_t rule_tap(const DasArgs& a, const LineGeom& L, const float4& E, int j) {
+  const int32_t b = a.depth_start + a.depth_step * j;
+  const float r = (float)b * a.h;
+  return fast_tap(a, b, small_tx_delay(L, r), E.x, E.y, r, r + r, r * r).i0;
+}
+
+__device__ inline float lo16(uint32_t d) { return float(int16_t(d & 0xffffu)); }
+__device__ inline float hi16(uint32_t d) { return float(int16_t(d >> 16)); }
+
+// One staging item: four consecutive samples of one element's window.  `voff` is the byte
+// offset of the first sample within the transmit's block of a frame (clamped into the
+// record); `dst` the window-relative LDS index of the first sample, with bits 26..29 saying
+// which of the four samples are inside the record; dst < 0: nothing to stage.
+constexpr int kDstMask = (1 << 26) - 1;
+
+template <int IPT>
+struct Items {
+  uint32_t voff[IPT];
+  int dst[IPT];
+};
+
+template <bool VEC, int G, int FS, int IPT>
+__device__ inline Items<IPT> chunk_items(const TileLds<G, FS>& t, const TileArgs& ta, const DasArgs& a, int c) {
+  Items<IPT> d;
+  const int quads = ta.span >> 2;
+  const int e0 = c * ta.ec;
+  const int ec = min(ta.ec, a.n_el - e0);
+  const int S = a.n_samples;
+#pragma unroll
+  for (int it = 0; it < IPT; ++it) {
+    const int item = threadIdx.x + it * kDasThreads;
+    const int k = item / quads, q = item - k * quads, e = e0 + k;
+    d.voff[it] = 0u;
+    d.dst[it] = -1;
+    if (item >= ec * quads || c < 0) continue;
+    const int2 wd = t.wnd[e];
+    const int i = wd.x + 4 * q;
+    if (!(t.flg[e] & 2) || i > wd.y) continue;
+    uint32_t in = 0u;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) in |= (i + s >= 0 && i + s < S) ? (1u << s) : 0u;
+    const int ic = VEC ? (in ? i : 0) : i;  // VEC: all four inside or all outside
+    d.voff[it] = uint32_t((size_t(e) * S + (ic < 0 ? 0 : ic)) * sizeof(int16_t));
+    d.dst[it] = (k * ta.span + (ta.pshift ? 2 * q : 4 * q)) | int(in << 26);
+  }
+  return d;
+}
+
+template <bool VEC, int FS, int IPT>
+struct Prefetch {
+  uint2 d[IPT][FS];
+};
+
+// Buffer resource over `base` (gfx9 raw buffer, no range clamping: every offset used is
+// inside the channel data).
+__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, int(0xffffffffu), 0x00020000);
+}
+
+// Global loads of one staging step: frames fr .. fr+FS-1 of the transmit block `rsrc` starts
+// at, `fbytes` bytes apart.  Each load is a buffer load with the lane's offset in a VGPR and
+// the frame's offset in an SGPR, so addressing costs no vector instructions.
+template <bool VEC, int FS, int IPT>
+__device__ inline void issue_stage(Prefetch<VEC, FS, IPT>& pf, const Items<IPT>& it_, __amdgpu_buffer_rsrc_t rsrc,
+                                   uint32_t fr_off, uint32_t fbytes, int S) {
+#pragma unroll
+  for (int it = 0; it < IPT; ++it) {
+#pragma unroll
+    for (int f = 0; f < FS; ++f) {
+      const uint32_t so = fr_off + uint32_t(f) * fbytes;
+      if constexpr (VEC) {
+        pf.d[it][f] = __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(rsrc, it_.voff[it], so, 0));
+      } else {
+        // samples one by one, each clamped into the record
+        const int i = int((it_.voff[it] / sizeof(int16_t)) % uint32_t(S));
+        uint32_t h[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const uint32_t o = it_.voff[it] + uint32_t((i + s < S) ? s : 0) * 2u;
+          h[s] = __builtin_amdgcn_raw_buffer_load_b16(rsrc, o, so, 0);
+        }
+        pf.d[it][f] = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+      }
+    }
+  }
+}
+
+template <bool VEC, int G, int FS, int IPT>
+__device__ inline void store_stage(const Prefetch<VEC, FS, IPT>& pf, const Items<IPT>& it_,
+                                   typename FVec<FS>::T* win, int span, int pshift) {
+  using V = typename FVec<FS>::T;
+  const int half = span >> 1;
+#pragma unroll
+  for (int it = 0; it < IPT; ++it) {
+    const int dst = it_.dst[it];
+    if (dst < 0) continue;
+    const uint32_t in = uint32_t(dst) >> 26;
+    const uint32_t m0 = (in & 1u) ? 0xffffu : 0u, m1 = (in & 2u) ? 0xffff0000u : 0u;
+    const uint32_t m2 = (in & 4u) ? 0xffffu : 0u, m3 = (in & 8u) ? 0xffff0000u : 0u;
+    V x[4];
+#pragma unroll
+    for (int f = 0; f < FS; ++f) {
+      const uint32_t dx = pf.d[it][f].x & (m0 | m1), dy = pf.d[it][f].y & (m2 | m3);
+      FVec<FS>::set(x[0], f, lo16(dx));
+      FVec<FS>::set(x[1], f, hi16(dx));
+      FVec<FS>::set(x[2], f, lo16(dy));
+      FVec<FS>::set(x[3], f, hi16(dy));
+    }
+    V* w = win + (dst & kDstMask);
+    if (pshift) {
+      w[0] = x[0];
+      w[1] = x[2];
+      w[half] = x[1];
+      w[half + 1] = x[3];
+    } else {
+      w[0] = x[0];
+      w[1] = x[1];
+      w[2] = x[2];
+      w[3] = x[3];
+    }
+  }
+}
+
+// Delay-and-sum for frames [frame0, frame0 + n_blocks * FB) of the batch.
+template <bool VEC, int G, int FB, int FS>
+__global__ __launch_bounds__(kDasThreads) void das_tile_kernel(const int16_t* __restrict__ rf, int frame0,
+                                                               int n_blocks, DasArgs a, TileArgs ta,
+                                                               float* __restrict__ out) {
+  using V = typename FVec<FS>::T;
+  using SH = Shape<G, FS>;
+  constexpr int TD = SH::TD;
+  constexpr int NS = FB / FS;
+  constexpr int IPT = SH::IPT;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const TileLds<G, FS> t = carve<G, FS>(lds_raw, a.n_el);
+
+  const int tid = threadIdx.x;
+  const uint32_t bid = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int group = int(bid / ta.n_dtiles);
+  const int dt = int(bid % ta.n_dtiles);
+  const int g = tid / TD;
+  const int l0 = group * G;
+  const int l = l0 + g;
+  const int j = dt * TD + tid % TD;
+  const int j_first = dt * TD;
+  const int j_last = min(a.n_depth, j_first + TD) - 1;
+  const bool line_ok = l < a.n_lines;
+  const bool pix_ok = line_ok && j < a.n_depth;
+  const int S = a.n_samples;
+  const int t0 = a.line_tx[l0];
+  const int t_grp = (t0 >= 0 && t0 < a.n_tx) ? t0 : -1;
+
+  // ---- prologue: line constants, per-(line, element) receive constants, tap windows
+  constexpr int ZERO = 2 * SH::BUFV;
+  if (tid < G) line_geom(a, min(l0 + tid, a.n_lines - 1), t.lines[tid]);
+  if (tid == 0) {
+    V z;
+#pragma unroll
+    for (int f = 0; f < FS; ++f) FVec<FS>::set(z, f, 0.0f);
+    t.win[ZERO] = z;
+  }
+  for (int e = tid; e < a.n_el; e += kDasThreads) {
+    t.wnd[e] = make_int2(INT_MAX, INT_MIN);
+    t.flg[e] = 0;
   }
   __syncthreads();
-  if (j >= a.n_depth) return;
-
-  const size_t line_stride = size_t(a.n_depth);
-  const size_t frame_out = size_t(a.n_lines) * line_stride;
-  float* o = out + size_t(l) * line_stride + j;
-  if (L.tx < 0) {
-    for (int f = 0; f < n_frames; ++f) o[f * frame_out] = 0.0f;
-    return;
+  for (int idx = tid; idx < a.n_el * G; idx += kDasThreads) {
+    const int gg = idx / a.n_el, e = idx - gg * a.n_el;
+    const ElemGeom E = elem_geom(a, t.lines[gg], e);
+    t.geo[gg * a.n_el + e] = make_float4(E.A, E.B, E.dx, E.dy);
   }
+  __syncthreads();
+  {
+    const float r_last = (float)(a.depth_start + a.depth_step * j_last) * a.h;
+    for (int idx = tid; idx < a.n_el * G; idx += kDasThreads) {
+      const int gg = idx / a.n_el, e = idx - gg * a.n_el;
+      const LineGeom& Lg = t.lines[gg];
+      if (l0 + gg >= a.n_lines || Lg.tx < 0) continue;
+      const float4 E4 = t.geo[gg * a.n_el + e];
+      const ElemGeom E{E4.x, E4.y, E4.z, E4.w};
+      if (!in_aperture(a, E, r_last)) continue;
+      if (Lg.tx != t_grp) {
+        atomicOr(&t.flg[e], 1);
+        continue;
+      }
+      atomicMin(&t.wnd[e].x, rule_tap(a, Lg, E4, j_first));
+      atomicMax(&t.wnd[e].y, rule_tap(a, Lg, E4, j_last) + 1);
+      atomicOr(&t.flg[e], 3);
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < a.n_el; e += kDasThreads) {
+    if (!(t.flg[e] & 2)) continue;
+    const int lo = t.wnd[e].x, hi = t.wnd[e].y;
+    int lo4 = lo >= 0 ? (lo & ~3) : -((-lo + 3) & ~3);   // align down to 4 samples
+    if (hi - lo4 + 1 > ta.span) {                          // wider than the buffer: keep the deep end
+      lo4 = hi + 1 - ta.span;
+      lo4 = lo4 >= 0 ? ((lo4 + 3) & ~3) : -((-lo4) & ~3);
+    }
+    t.wnd[e].x = lo4;
+  }
+  __syncthreads();
+
+  // ---- this lane's pixel
+  const LineGeom& L = t.lines[g];
+  const bool on_grp = line_ok && L.tx >= 0 && L.tx == t_grp;
+  const bool lane_ok = pix_ok && L.tx >= 0;
   const int32_t b = a.depth_start + a.depth_step * j;
   const float r = (float)b * a.h;
   const float r2 = r + r;
   const float rr = r * r;
   const float dtx = small_tx_delay(L, r);
   const float inv_w = r > 0.0f ? a.f_number / r : 0.0f;
-  const int S = a.n_samples;
-  const size_t frame_stride = size_t(a.n_tx) * a.n_el * S;
-  const int16_t* trace0 = rf + size_t(L.tx) * a.n_el * S;
+  const size_t tx_block = size_t(a.n_el) * S;              // samples per transmit
+  const size_t frame_stride = size_t(a.n_tx) * tx_block;   // samples per frame
+  const int16_t* grp_block = rf + size_t(t_grp < 0 ? 0 : t_grp) * tx_block;
+  const int16_t* own_block = rf + size_t(L.tx < 0 ? 0 : L.tx) * tx_block;
+  const float4* geo = t.geo + g * a.n_el;
+  const int n_chunks = (a.n_el + ta.ec - 1) / ta.ec;
+  const int half = ta.span >> 1;
 
-  for (int f0 = 0; f0 < n_frames; f0 += FB) {
+  auto chunk_needed = [&](int c) {
+    int any = 0;
+    for (int k = 0; k < ta.ec && c * ta.ec + k < a.n_el; ++k) any |= t.flg[c * ta.ec + k];
+    return any != 0;
+  };
+  auto next_chunk = [&](int c) {
+    for (++c; c < n_chunks; ++c)
+      if (chunk_needed(c)) return c;
+    return n_chunks;
+  };
+  const uint32_t fbytes = uint32_t(std::min<uint64_t>(frame_stride * sizeof(int16_t), 0xffffffffull));
+
+  Prefetch<VEC, FS, IPT> pf;
+  for (int blk = 0; blk < n_blocks; ++blk) {
+    const int fb = frame0 + blk * FB;
+    const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(grp_block + size_t(fb) * frame_stride);
     float acc[FB];
 #pragma unroll
     for (int f = 0; f < FB; ++f) acc[f] = 0.0f;
     float den = 0.0f;
-    const int nf = min(FB, n_frames - f0);
-    const int16_t* tr = trace0 + size_t(f0) * frame_stride;
-    for (int e = 0; e < a.n_el; ++e) {
-      const float4 c = s_el[e];
-      ElemGeom E{c.x, c.y, c.z, c.w};
-      if (!in_aperture(a, E, r)) continue;
-      const float w = apod_weight(a.window, a.array_dims, E.dx, E.dy, inv_w);
-      den += w;
-      const float drx = small_rx_delay(E.A, E.B, r, r2, rr);
-      const Tap t = delay_tap(a, b, dtx, drx);
-      if (t.i0 < 0 || t.i0 > S - 2) continue;
-      const float w1 = w * t.phi;
-      const float w0 = w - w1;
-      const int16_t* p = tr + size_t(e) * S + t.i0;
+    int cur = 0;
+    int c = next_chunk(-1);
+    const bool stage_any = t_grp >= 0;
+    Items<IPT> items = chunk_items<VEC, G, FS, IPT>(t, ta, a, c < n_chunks && stage_any ? c : -1);
+    issue_stage<VEC, FS, IPT>(pf, items, rsrc, 0u, fbytes, S);
+    store_stage<VEC, G, FS, IPT>(pf, items, t.win, ta.span, ta.pshift);
+    __syncthreads();
+    while (c < n_chunks) {
+      const int e0 = c * ta.ec;
+      const int cn = next_chunk(c);
+      const Items<IPT> next_items =
+          chunk_items<VEC, G, FS, IPT>(t, ta, a, cn < n_chunks && stage_any ? cn : -1);
+      // taps of this lane's pixel for the chunk's elements, shared by every frame; a tap that
+      // contributes nothing, or whose samples are not staged, reads the zero vector
+      int off0[SH::EC], off1[SH::EC];
+      float w0[SH::EC], w1[SH::EC];
+      uint32_t slow = 0u;
 #pragma unroll
-      for (int f = 0; f < FB; ++f) {
-        if (f < nf) {
-          const int16_t* q = p + f * frame_stride;
-          acc[f] = __builtin_fmaf(w0, (float)q[0], __builtin_fmaf(w1, (float)q[1], acc[f]));
+      for (int k = 0; k < SH::EC; ++k) {
+        off0[k] = off1[k] = ZERO;
+        w0[k] = w1[k] = 0.0f;
+        if (k >= ta.ec) continue;
+        const int e = min(e0 + k, a.n_el - 1);
+        const float4 E4 = geo[e];
+        const ElemGeom E{E4.x, E4.y, E4.z, E4.w};
+        const bool act = lane_ok && e0 + k < a.n_el && in_aperture(a, E, r);
+        if (!__any(act)) continue;  // no lane of the wave needs this element
+        const float w = act ? apod_weight(a.window, a.array_dims, E.dx, E.dy, inv_w) : 0.0f;
+        den += w;
+        const Tap tp = fast_tap(a, b, dtx, E.A, E.B, r, r2, rr);
+        const bool ok = act && tp.i0 >= 0 && tp.i0 <= S - 2;
+        const float wp = w * tp.phi;
+        w1[k] = ok ? wp : 0.0f;
+        w0[k] = ok ? w - wp : 0.0f;
+        const int2 wd = t.wnd[e];
+        const int rel = tp.i0 - wd.x;
+        const bool in_win = on_grp && (t.flg[e] & 2) && rel >= 0 && tp.i0 + 1 <= wd.y && rel + 1 < ta.span;
+        const int wbase = k * ta.span;
+        const int p0 = ta.pshift ? ((rel & 1) * half + (rel >> 1)) : rel;
+        const int p1 = ta.pshift ? (((rel + 1) & 1) * half + ((rel + 1) >> 1)) : rel + 1;
+        off0[k] = (ok && in_win) ? wbase + p0 : ZERO;
+        off1[k] = (ok && in_win) ? wbase + p1 : ZERO;
+        slow |= (ok && !in_win) ? (1u << k) : 0u;
+      }
+      // keep the scheduler from interleaving the tap set-up with the frame stages (it would
+      // hoist LDS reads across it and run out of registers)
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int buf = (NS % 2 == 0) ? (s & 1) : cur;
+        // prefetch the next step: this chunk's next frame stage, or the next chunk's first
+        const bool last = (s + 1 == NS);
+        const bool has_next = last ? (cn < n_chunks && stage_any) : stage_any;
+        const Items<IPT>& nit = last ? next_items : items;
+        if (has_next) issue_stage<VEC, FS, IPT>(pf, nit, rsrc, last ? 0u : uint32_t((s + 1) * FS) * fbytes, fbytes, S);
+        const V* w = t.win + buf * SH::BUFV;
+#pragma unroll
+        for (int k = 0; k < SH::EC; ++k) {
+          // the zero vector sits after both buffers: index relative to this buffer
+          const int i0 = off0[k] == ZERO ? ZERO - buf * SH::BUFV : off0[k];
+          const int i1 = off1[k] == ZERO ? ZERO - buf * SH::BUFV : off1[k];
+          const V x0 = w[i0];
+          const V x1 = w[i1];
+#pragma unroll
+          for (int f = 0; f < FS; ++f)
+            acc[s * FS + f] = __builtin_fmaf(w0[k], FVec<FS>::get(x0, f),
+                                             __builtin_fmaf(w1[k], FVec<FS>::get(x1, f), acc[s * FS + f]));
+        }
+        // pin this stage's sums here: otherwise the accumulation may be sunk below later stages,
+        // keeping every stage's LDS reads alive at once
+#pragma unroll
+        for (int f = 0; f < FS; ++f) asm volatile("" : "+v"(acc[s * FS + f]));
+        __builtin_amdgcn_sched_barrier(0);
+        if (has_next) store_stage<VEC, G, FS, IPT>(pf, nit, t.win + (buf ^ 1) * SH::BUFV, ta.span, ta.pshift);
+        __syncthreads();
+        if (NS % 2 != 0) cur ^= 1;
+      }
+      if (slow) {  // taps outside the staged windows: read global memory
+        for (int k = 0; k < ta.ec; ++k) {
+          if (!(slow & (1u << k))) continue;
+          const float4 E4 = geo[e0 + k];
+          const Tap tp = fast_tap(a, b, dtx, E4.x, E4.y, r, r2, rr);
+          const int16_t* p = own_block + size_t(e0 + k) * S + tp.i0;
+          float sw0 = 0.0f, sw1 = 0.0f;
+#pragma unroll
+          for (int kk = 0; kk < SH::EC; ++kk)
+            if (kk == k) {
+              sw0 = w0[kk];
+              sw1 = w1[kk];
+            }
+#pragma unroll
+          for (int f = 0; f < FB; ++f) {
+            const int16_t* q = p + size_t(fb + f) * frame_stride;
+            acc[f] = __builtin_fmaf(sw0, float(q[0]), __builtin_fmaf(sw1, float(q[1]), acc[f]));
+          }
         }
       }
+      items = next_items;
+      c = cn;
     }
-    const float inv = den > 0.0f ? 1.0f / den : 0.0f;
+    if (pix_ok) {
+      const float inv = den > 0.0f ? 1.0f / den : 0.0f;
+      float* o = out + size_t(l) * a.n_depth + j;
+      const size_t frame_out = size_t(a.n_lines) * a.n_depth;
 #pragma unroll
-    for (int f = 0; f < FB; ++f)
-      if (f < nf) o[size_t(f0 + f) * frame_out] = acc[f] * inv;
+      for (int f = 0; f < FB; ++f) o[size_t(fb + f) * frame_out] = acc[f] * inv;
+    }
+    __syncthreads();
   }
 }
 
@@ -96,37 +476,74 @@ __global__ void delay_index_kernel(DasArgs a, int32_t* __restrict__ i0, uint8_t*
     const float rr = r * r;
     const float dtx = small_tx_delay(L, r);
     ElemGeom E = elem_geom(a, L, e);
-    const float drx = small_rx_delay(E.A, E.B, r, r2, rr);
-    const Tap t = delay_tap(a, b, dtx, drx);
+    // the index through the beamformer's own path (fast evaluation with exact fallback),
+    // the fraction from the rule itself
+    const Tap t = fast_tap(a, b, dtx, E.A, E.B, r, r2, rr);
     const bool act = in_aperture(a, E, r);
     const bool val = t.i0 >= 0 && t.i0 <= a.n_samples - 2;
     i0[idx] = t.i0;
     flags[idx] = uint8_t((act ? 1 : 0) | (val ? 2 : 0));
-    if (phi) phi[idx] = t.phi;
+    if (phi) phi[idx] = delay_tap(a, b, dtx, small_rx_delay(E.A, E.B, r, r2, rr)).phi;
   }
 }
 
-template <int FB>
-static void launch_das(const int16_t* rf, int n_frames, const DasArgs& a, float* out, hipStream_t s) {
-  dim3 grid((a.n_depth + kDasThreads - 1) / kDasThreads, a.n_lines);
-  size_t lds = size_t(a.n_el) * sizeof(float4);
-  hipLaunchKernelGGL(das_gather_kernel<FB>, grid, dim3(kDasThreads), lds, s, rf, n_frames, a, out);
+template <int G, int FB, int FS>
+static int launch_das(const int16_t* rf, int frame0, int n_blocks, const DasArgs& a, float* out, hipStream_t s) {
+  using SH = Shape<G, FS>;
+  TileArgs ta;
+  ta.span = (a.depth_step * SH::TD + kWindowMargin + 3) & ~3;
+  ta.ec = std::min(SH::EC, SH::BUFV / ta.span);
+  if (ta.ec < 1) {  // very large depth_step: one element per chunk, windows capped
+    ta.ec = 1;
+    ta.span = SH::BUFV & ~3;
+  }
+  ta.pshift = (a.depth_step % 2 == 0) ? 1 : 0;
+  ta.n_dtiles = (a.n_depth + SH::TD - 1) / SH::TD;
+  const int64_t blocks = int64_t((a.n_lines + G - 1) / G) * ta.n_dtiles;
+  if (blocks > 0x7fffffff) return fail(USBF_EUNSUPPORTED, "too many tiles");
+  const size_t lds = tile_lds_bytes<G, FS>(a.n_el);
+  if (lds > 65536) return fail(USBF_EUNSUPPORTED, "%d elements need %zu bytes of LDS per tile", a.n_el, lds);
+  const bool vec = (a.n_samples % 4) == 0 && (reinterpret_cast<uintptr_t>(rf) & 7) == 0;
+  if (vec)
+    hipLaunchKernelGGL((das_tile_kernel<true, G, FB, FS>), dim3(unsigned(blocks)), dim3(kDasThreads), lds, s, rf,
+                       frame0, n_blocks, a, ta, out);
+  else
+    hipLaunchKernelGGL((das_tile_kernel<false, G, FB, FS>), dim3(unsigned(blocks)), dim3(kDasThreads), lds, s, rf,
+                       frame0, n_blocks, a, ta, out);
+  return check_launch("das_tile_kernel");
+}
+
+// Frames are processed in blocks of FB sharing one evaluation of the delays; the batch is
+// split into launches of whole blocks, largest first (e.g. 37 = 32 + 4 + 1).
+template <int G>
+static int launch_das_g(const int16_t* rf, int n_frames, const DasArgs& a, float* out, hipStream_t s) {
+  int f0 = 0, st = USBF_OK;
+  const uint64_t frame_bytes = uint64_t(a.n_tx) * a.n_el * a.n_samples * sizeof(int16_t);
+  auto run = [&](int FB, auto fn) {
+    // frame offsets inside a block are 32-bit buffer offsets
+    if (uint64_t(FB - 1) * frame_bytes > 0xffffffffull) return;
+    const int nb = (n_frames - f0) / FB;
+    if (nb > 0 && st == USBF_OK) {
+      st = fn(f0, nb);
+      f0 += nb * FB;
+    }
+  };
+  run(32, [&](int f, int nb) { return launch_das<G, 32, 4>(rf, f, nb, a, out, s); });
+  run(16, [&](int f, int nb) { return launch_das<G, 16, 4>(rf, f, nb, a, out, s); });
+  run(8, [&](int f, int nb) { return launch_das<G, 8, 4>(rf, f, nb, a, out, s); });
+  run(4, [&](int f, int nb) { return launch_das<G, 4, 4>(rf, f, nb, a, out, s); });
+  run(2, [&](int f, int nb) { return launch_das<G, 2, 2>(rf, f, nb, a, out, s); });
+  run(1, [&](int f, int nb) { return launch_das<G, 1, 1>(rf, f, nb, a, out, s); });
+  return st;
 }
 
 int beamform_enqueue(const int16_t* rf, int32_t n_frames, const DasArgs& a, float* out, hipStream_t s) {
-  if (n_frames >= 32)
-    launch_das<32>(rf, n_frames, a, out, s);
-  else if (n_frames >= 16)
-    launch_das<16>(rf, n_frames, a, out, s);
-  else if (n_frames >= 8)
-    launch_das<8>(rf, n_frames, a, out, s);
-  else if (n_frames >= 4)
-    launch_das<4>(rf, n_frames, a, out, s);
-  else if (n_frames >= 2)
-    launch_das<2>(rf, n_frames, a, out, s);
-  else
-    launch_das<1>(rf, n_frames, a, out, s);
-  return check_launch("das_gather_kernel");
+  switch (a.lines_per_tx) {
+    case 2: return launch_das_g<2>(rf, n_frames, a, out, s);
+    case 4: return launch_das_g<4>(rf, n_frames, a, out, s);
+    case 8: return launch_das_g<8>(rf, n_frames, a, out, s);
+    default: return launch_das_g<1>(rf, n_frames, a, out, s);
+  }
 }
 
 }  // namespace usbf

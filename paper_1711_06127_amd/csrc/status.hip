@@ -52,6 +52,8 @@ int make_das_args(const usbf_geometry* g, const usbf_rx* rx, DasArgs* a) {
   a->n_tx = g->n_tx;
   a->n_lines = g->n_lines;
   a->array_dims = g->array_dims;
+  USBF_REQUIRE(g->lines_per_tx >= 0, USBF_EINVAL, "lines_per_tx must be >= 0");
+  a->lines_per_tx = g->lines_per_tx;
   a->n_samples = rx->n_samples;
   a->depth_start = rx->depth_start;
   a->depth_step = rx->depth_step;

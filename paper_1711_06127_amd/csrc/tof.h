@@ -138,6 +138,37 @@ __device__ inline Tap delay_tap(const DasArgs& a, int32_t b, float dtx, float dr
   return t;
 }
 
+// The same tap, computed with the hardware square root and reciprocal (each within 1 ulp)
+// instead of the correctly rounded ones.  Let u = 2^-24.  The fast receive delay differs from
+// the rule's by at most 9u relative (3u for the rule's sqrt/add/divide, 6u for the fast
+// sqrt/add/reciprocal/multiply), and the three further roundings of dtx + drx, K (.) and
+// - T0 add at most 2u of each intermediate, so
+//   |dt_fast - dt_rule| <= u (10 K|drx| + 4 K|dtx + drx| + 2 |dt|)     (first order).
+// Twice that bound is used as a guard band: outside it floor(dt_fast) = floor(dt_rule) and the
+// fast value is kept (phi then differs from the rule's by less than the band); inside it the
+// rule itself is evaluated.  The integer index is therefore always the rule's.
+__device__ inline Tap fast_tap(const DasArgs& a, int32_t b, float dtx, float A, float B, float r, float r2,
+                               float rr) {
+  const float q = A - r2 * B;
+  float X = q + rr;
+  X = (X > 0.0f) ? X : 0.0f;
+  const float s = __builtin_amdgcn_sqrtf(X) + r;
+  const float drx = (s > 0.0f) ? q * __builtin_amdgcn_rcpf(s) : 0.0f;
+  const float D = dtx + drx;
+  const float KD = a.K * D;
+  const float d = KD - a.T0;
+  const float fl = floorf(d);
+  const float fr = d - fl;
+  const float eps = 1.1920929e-07f * (20.0f * fabsf(a.K * drx) + 8.0f * fabsf(KD) + 4.0f * fabsf(d)) + 1e-30f;
+  Tap t;
+  if (fr > eps && fr < 1.0f - eps) {
+    t.phi = fr;
+    t.i0 = b + (int32_t)fl;
+    return t;
+  }
+  return delay_tap(a, b, dtx, small_rx_delay(A, B, r, r2, rr));
+}
+
 __device__ inline bool in_aperture(const DasArgs& a, const ElemGeom& E, float r) {
   bool act = a.F2 * fabsf(E.dx) <= r;
   if (a.array_dims == 2) act = act && (a.F2 * fabsf(E.dy) <= r);

@@ -47,7 +47,7 @@ FAKE = 0x10000  # never dereferenced: every call below fails validation first
 
 
 def geom(u, n_el=4, n_tx=2, n_lines=3, dims=1):
-    return u.CGeometry(n_el, FAKE, n_tx, FAKE, FAKE, FAKE, n_lines, FAKE, FAKE, FAKE, dims)
+    return u.CGeometry(n_el, FAKE, n_tx, FAKE, FAKE, FAKE, n_lines, FAKE, FAKE, FAKE, dims, 0)
 
 
 def rx(u, **kw):
