@@ -199,11 +199,124 @@ int usbf_bmode(const int16_t* rf, int32_t n_frames, const usbf_geometry* geom, c
                const usbf_scan* scan, float dyn_range_db, float* image, void* ws, size_t ws_bytes,
                hipStream_t stream);
 
+/* ---------------------------------------------------------------- adaptive apodization */
+
+/*
+ * Delayed channel samples (the beamformer's taps without weights or summation): for each
+ * listed pixel, every element's channel sample linearly interpolated at the two-way travel
+ * time of the binary32 delay rule (usbf_delay_index_map), 0 outside the record.  Input to the
+ * minimum-variance weights and the learned apodization below; an extension beyond the
+ * paper's delay-and-sum (Sec. 2 method list item 2).
+ *   rf   int16 [n_frames][n_tx][n_el][n_samples]
+ *   pix  int32 [n_pix][3] (frame, line, depth index); entries out of range give a row of zeros
+ *   x    float [n_pix][n_el]
+ */
+int usbf_delay_gather(const int16_t* rf, int32_t n_frames, const usbf_geometry* geom, const usbf_rx* rx,
+                      const int32_t* pix, int32_t n_pix, float* x, hipStream_t stream);
+
+/*
+ * Minimum-variance (Capon) apodization per pixel, spatially smoothed over subapertures of
+ * `subap` elements with diagonal loading (Synnevaag, Austeng and Holm 2007):
+ *   R = (1/K) sum_l x_l x_l^T, x_l = x[l .. l+subap-1], K = n_el - subap + 1  (binary32)
+ *   (R + loading * trace(R)/subap * I) v = 1 by Cholesky factorisation     (binary64)
+ *   w = v / 1^T v;  w_full[e] = (1/K) sum_{l: 0 <= e-l < subap} w[e-l];  y = w_full^T x
+ *   (a pixel whose samples are all zero gets loading 1 in place of loading * trace / subap,
+ *   i.e. uniform weights)
+ *   x      float [n_pix][n_el];  w_full float [n_pix][n_el] or NULL;  y float [n_pix] or NULL.
+ * subap must be 32 and subap <= n_el <= 256.
+ */
+int usbf_mv_weights(const float* x, int32_t n_pix, int32_t n_el, int32_t subap, float loading,
+                    float* w_full, float* y, hipStream_t stream);
+
+/*
+ * Learned apodization: a 1D convolutional network -- four layers, 32 channels, kernel 5,
+ * ReLU between layers, "same" zero padding -- maps the delayed samples x of a pixel
+ * (normalised by their RMS) to one weight per element; trained to reproduce minimum-variance
+ * weights (loss = mean over pixels and elements of (n_el w - n_el w_target)^2, Adam with
+ * beta 0.9 / 0.999, eps 1e-8).  All products run on the matrix cores with bfloat16 operands
+ * (layer inputs, weights and back-propagated gradients rounded to nearest even) and binary32
+ * accumulation; the master weights are binary32.
+ *   state   caller-owned device buffer of usbf_apodnet_state_bytes(): parameters, Adam moments,
+ *           step count and the weights packed for the matrix cores.
+ *   params  float [10657] = W1[32][1][5] b1[32] W2[32][32][5] b2[32] W3[32][32][5] b3[32]
+ *           W4[1][32][5] b4[1] (device), copied in by usbf_apodnet_init (moments reset).
+ *   x, w, w_target  float [n_pix][n_el], n_el a multiple of 32 in 32..256 (LDS-resident rows).
+ *   ws      workspace of usbf_workspace_bytes(USBF_OP_APODNET[_TRAIN], n_pix, n_el, 0) bytes.
+ *   loss    device float receiving the step's loss (before the update), or NULL.
+ * usbf_apodnet_gradients returns the loss gradient [10657] without updating anything.
+ */
+size_t usbf_apodnet_state_bytes(void);
+int32_t usbf_apodnet_num_params(void);
+int usbf_apodnet_init(void* state, const float* params, hipStream_t stream);
+int usbf_apodnet_forward(const void* state, const float* x, int32_t n_pix, int32_t n_el, float* w, void* ws,
+                         size_t ws_bytes, hipStream_t stream);
+int usbf_apodnet_train_step(void* state, const float* x, const float* w_target, int32_t n_pix, int32_t n_el,
+                            float lr, float* loss, void* ws, size_t ws_bytes, hipStream_t stream);
+int usbf_apodnet_gradients(const void* state, const float* x, const float* w_target, int32_t n_pix, int32_t n_el,
+                           float* grad, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Adaptively weighted sum: y[p] = sum_e w[p][e] x[p][e]; a pixel whose weights are not all
+ * finite takes y_fallback[p] (the delay-and-sum value), if given.
+ */
+int usbf_beamform_weighted(const float* x, const float* w, const float* y_fallback, int32_t n_pix, int32_t n_el,
+                           float* y, hipStream_t stream);
+
+/* ---------------------------------------------------------------- batched, persistent */
+
+/*
+ * A batch of frames and volumes of different sizes, taken through the whole pipeline
+ * (delay and sum -> envelope -> log compression -> scan conversion) by one persistent
+ * delay-and-sum launch followed by the per-item epilogues, captured once in a HIP graph and
+ * replayed by usbf_batch_run.  For streams of acquisitions whose geometry repeats (Sec. 4
+ * runs every acquisition through the same node graph).
+ *   rf       int16 [n_tx][n_el][n_samples], one frame or volume
+ *   lines    float [n_lines][n_depth], receives the beamformed lines, then their envelope
+ *   row_max  float [n_lines]
+ *   image    float [grid] B-mode, reference = the item's maximum, dyn_range_db below it -> 0
+ * All buffers are caller-owned device memory that must stay valid while the plan exists;
+ * their contents (rf) may change between runs.  n_samples must be a multiple of 4 for every
+ * item or for none; n_depth must satisfy usbf_envelope's length rule.
+ */
+typedef struct usbf_batch_item {
+  const int16_t* rf;
+  usbf_geometry geom;
+  usbf_rx rx;
+  usbf_scan scan;
+  float dyn_range_db;
+  float* lines;
+  float* row_max;
+  float* image;
+} usbf_batch_item;
+
+typedef struct usbf_batch_plan usbf_batch_plan;
+
+/*
+ * Validates the items, uploads their descriptors, orders the work units (most expensive
+ * items first), and captures the graph on `stream`.  tune_cache: path of a JSON file written
+ * by usbf_autotune (NULL or missing entry: default launch shape).  The plan owns a few KB of
+ * device memory and a graph; it is not thread-safe.
+ */
+int usbf_batch_plan_create(const usbf_batch_item* items, int32_t n_items, const char* tune_cache,
+                           usbf_batch_plan** plan, hipStream_t stream);
+int usbf_batch_run(usbf_batch_plan* plan, hipStream_t stream);
+int usbf_batch_plan_destroy(usbf_batch_plan* plan);
+/* Launch shape chosen for the plan: workgroups per compute unit and ordering (1 = by cost). */
+int usbf_batch_plan_shape(const usbf_batch_plan* plan, int32_t* groups_per_cu, int32_t* cost_order);
+
+/*
+ * Times the batch with every candidate launch shape (workgroups per compute unit x unit
+ * ordering) by graph replays and records the fastest in the JSON file `tune_cache`, keyed by
+ * the device architecture and a signature of the item sizes.  Synchronises `stream`.
+ */
+int usbf_autotune(const usbf_batch_item* items, int32_t n_items, const char* tune_cache, hipStream_t stream);
+
 #define USBF_OP_LOG_COMPRESS 1
 #define USBF_OP_LOG_SCAN     2
 #define USBF_OP_BMODE        3
 #define USBF_OP_MV           4
 #define USBF_OP_APODNET      5
+#define USBF_OP_APODNET_TRAIN 6
 
 /* Workspace bytes needed by operation `op` for the given sizes (0 if none). */
 size_t usbf_workspace_bytes(int32_t op, int64_t n_frames, int64_t n_lines, int64_t n_depth);

@@ -46,6 +46,11 @@ class CScan(ctypes.Structure):
                 ("n_u", I32), ("n_v", I32), ("r0", F32), ("dr", F32), ("n_depth", I32), ("fill", F32)]
 
 
+class CBatchItem(ctypes.Structure):
+    _fields_ = [("rf", P), ("geom", CGeometry), ("rx", CRx), ("scan", CScan), ("dyn_range_db", F32),
+                ("lines", P), ("row_max", P), ("image", P)]
+
+
 # name -> (restype, argtypes)
 _SIGS = {
     "usbf_beamform": (I32, [P, I32, P, P, P, P]),
@@ -57,6 +62,20 @@ _SIGS = {
     "usbf_workspace_bytes": (ctypes.c_size_t, [I32, I64, I64, I64]),
     "usbf_delay_index_map": (I32, [P, P, P, P, P, P]),
     "usbf_scan_index_map": (I32, [P, P, P]),
+    "usbf_delay_gather": (I32, [P, I32, P, P, P, I32, P, P]),
+    "usbf_mv_weights": (I32, [P, I32, I32, I32, F32, P, P, P]),
+    "usbf_apodnet_state_bytes": (ctypes.c_size_t, []),
+    "usbf_apodnet_num_params": (I32, []),
+    "usbf_apodnet_init": (I32, [P, P, P]),
+    "usbf_apodnet_forward": (I32, [P, P, I32, I32, P, P, ctypes.c_size_t, P]),
+    "usbf_apodnet_train_step": (I32, [P, P, P, I32, I32, F32, P, P, ctypes.c_size_t, P]),
+    "usbf_apodnet_gradients": (I32, [P, P, P, I32, I32, P, P, ctypes.c_size_t, P]),
+    "usbf_beamform_weighted": (I32, [P, P, P, I32, I32, P, P]),
+    "usbf_batch_plan_create": (I32, [P, I32, ctypes.c_char_p, P, P]),
+    "usbf_batch_run": (I32, [P, P]),
+    "usbf_batch_plan_destroy": (I32, [P]),
+    "usbf_batch_plan_shape": (I32, [P, P, P]),
+    "usbf_autotune": (I32, [P, I32, ctypes.c_char_p, P]),
     "usbf_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "usbf_last_error_detail": (ctypes.c_char_p, []),
     "usbf_version": (ctypes.c_char_p, []),
@@ -272,3 +291,169 @@ def scan_index_map(dg: DeviceGeometry) -> torch.Tensor:
     base = torch.empty(dg.scan_shape, dtype=torch.int32, device=dg.device)
     _check(lib().usbf_scan_index_map(ctypes.byref(dg.scan), _ptr(base), _stream(dg.device)))
     return base
+
+
+def delay_gather(rf: torch.Tensor, dg: DeviceGeometry, pix: torch.Tensor, out: torch.Tensor | None = None):
+    """Delayed channel samples x [n_pix, n_el] for pixels pix int32 [n_pix, 3] (frame, line, depth)."""
+    _need_cuda(rf, "rf", torch.int16)
+    if rf.dim() == 3:
+        rf = rf.unsqueeze(0)
+    _need_cuda(pix, "pix", torch.int32)
+    n = pix.shape[0]
+    if out is None:
+        out = torch.empty((n, dg.n_el), dtype=torch.float32, device=rf.device)
+    _check(lib().usbf_delay_gather(_ptr(rf), rf.shape[0], ctypes.byref(dg.geom), ctypes.byref(dg.rx), _ptr(pix), n,
+                                   _ptr(out), _stream(rf.device)))
+    return out
+
+
+def mv_weights(x: torch.Tensor, subap: int = 32, loading: float = 1e-2, want_weights: bool = True):
+    """Minimum-variance weights (w_full [n_pix, n_el] or None, y [n_pix]) of delayed samples x."""
+    _need_cuda(x, "x", torch.float32)
+    n, m = x.shape
+    wf = torch.empty_like(x) if want_weights else None
+    y = torch.empty(n, dtype=torch.float32, device=x.device)
+    _check(lib().usbf_mv_weights(_ptr(x), n, m, subap, loading, _ptr(wf), _ptr(y), _stream(x.device)))
+    return wf, y
+
+
+OP_APODNET_TRAIN = 6
+
+# flattened parameter layout of the apodization network
+NET_LAYOUT = [("W1", (32, 1, 5)), ("b1", (32,)), ("W2", (32, 32, 5)), ("b2", (32,)),
+              ("W3", (32, 32, 5)), ("b3", (32,)), ("W4", (1, 32, 5)), ("b4", (1,))]
+
+
+def flatten_params(params: dict) -> np.ndarray:
+    return np.concatenate([np.asarray(params[k], np.float32).reshape(-1) for k, _ in NET_LAYOUT])
+
+
+def unflatten_params(flat) -> dict:
+    flat = np.asarray(flat, np.float32)
+    out, o = {}, 0
+    for k, shp in NET_LAYOUT:
+        n = int(np.prod(shp))
+        out[k] = flat[o:o + n].reshape(shp)
+        o += n
+    return out
+
+
+class ApodNet:
+    """Device state of the learned-apodization network (parameters, Adam moments, packed
+    weights) and a reusable workspace."""
+
+    def __init__(self, params: dict, device="cuda"):
+        self.device = torch.device(device)
+        self.state = torch.zeros(int(lib().usbf_apodnet_state_bytes()), dtype=torch.uint8, device=self.device)
+        flat = torch.as_tensor(flatten_params(params), device=self.device)
+        _check(lib().usbf_apodnet_init(_ptr(self.state), _ptr(flat), _stream(self.device)))
+        torch.cuda.current_stream(self.device).synchronize()
+        self._ws = None
+
+    def params(self) -> dict:
+        n = int(lib().usbf_apodnet_num_params())
+        flat = self.state[: 4 * n].view(torch.float32).cpu().numpy()
+        return unflatten_params(flat)
+
+    def _workspace(self, n_pix, n_el, train):
+        need = workspace_bytes(OP_APODNET_TRAIN if train else OP_APODNET, n_pix, n_el, 0)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = _ws(need, self.device)
+        return self._ws
+
+    def forward(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        _need_cuda(x, "x", torch.float32)
+        n, m = x.shape
+        if out is None:
+            out = torch.empty_like(x)
+        ws = self._workspace(n, m, False)
+        _check(lib().usbf_apodnet_forward(_ptr(self.state), _ptr(x), n, m, _ptr(out), _ptr(ws), ws.numel(),
+                                          _stream(x.device)))
+        return out
+
+    def train_step(self, x: torch.Tensor, target: torch.Tensor, lr: float = 1e-3,
+                   loss: torch.Tensor | None = None):
+        _need_cuda(x, "x", torch.float32)
+        _need_cuda(target, "target", torch.float32)
+        n, m = x.shape
+        ws = self._workspace(n, m, True)
+        _check(lib().usbf_apodnet_train_step(_ptr(self.state), _ptr(x), _ptr(target), n, m, lr, _ptr(loss),
+                                             _ptr(ws), ws.numel(), _stream(x.device)))
+        return loss
+
+    def gradients(self, x: torch.Tensor, target: torch.Tensor) -> torch.Tensor:
+        n, m = x.shape
+        grad = torch.empty(int(lib().usbf_apodnet_num_params()), dtype=torch.float32, device=x.device)
+        ws = self._workspace(n, m, True)
+        _check(lib().usbf_apodnet_gradients(_ptr(self.state), _ptr(x), _ptr(target), n, m, _ptr(grad), _ptr(ws),
+                                            ws.numel(), _stream(x.device)))
+        return grad
+
+
+def beamform_weighted(x: torch.Tensor, w: torch.Tensor, fallback: torch.Tensor | None = None) -> torch.Tensor:
+    _need_cuda(x, "x", torch.float32)
+    _need_cuda(w, "w", torch.float32)
+    n, m = x.shape
+    y = torch.empty(n, dtype=torch.float32, device=x.device)
+    _check(lib().usbf_beamform_weighted(_ptr(x), _ptr(w), _ptr(fallback), n, m, _ptr(y), _stream(x.device)))
+    return y
+
+
+class BatchPlan:
+    """A batch of acquisitions of different geometries taken through the whole B-mode pipeline by
+    one persistent delay-and-sum launch plus per-item epilogues, captured once as a HIP graph.
+
+    items: list of (rf int16 [n_tx, n_el, n_samples], DeviceGeometry).  The plan owns the line,
+    row-maximum and image buffers (``lines[i]``, ``images[i]``); write new channel data into the
+    rf tensors in place and call ``run()``.
+    """
+
+    def __init__(self, items, dyn_range_db: float = 50.0, tune_cache: str | None = None, autotune: bool = False):
+        self._plan = None
+        self.rf, self.dgs, self.lines, self.row_max, self.images = [], [], [], [], []
+        arr = (CBatchItem * len(items))()
+        for k, (rf, dg) in enumerate(items):
+            _need_cuda(rf, "rf", torch.int16)
+            if rf.dim() == 4:
+                if rf.shape[0] != 1:
+                    raise ValueError("batch items hold one frame each")
+                rf = rf[0]
+            lines = torch.empty((dg.n_lines, dg.n_depth), dtype=torch.float32, device=rf.device)
+            rmax = torch.empty((dg.n_lines,), dtype=torch.float32, device=rf.device)
+            img = torch.empty(dg.scan_shape, dtype=torch.float32, device=rf.device)
+            self.rf.append(rf)
+            self.dgs.append(dg)
+            self.lines.append(lines)
+            self.row_max.append(rmax)
+            self.images.append(img)
+            arr[k] = CBatchItem(_ptr(rf), dg.geom, dg.rx, dg.scan, dyn_range_db, _ptr(lines), _ptr(rmax), _ptr(img))
+        self._items = arr
+        self.device = items[0][0].device
+        cache = tune_cache.encode() if tune_cache else None
+        if autotune:
+            if not tune_cache:
+                raise ValueError("autotune needs a tune_cache path")
+            _check(lib().usbf_autotune(arr, len(items), cache, _stream(self.device)))
+        plan = ctypes.c_void_p()
+        _check(lib().usbf_batch_plan_create(arr, len(items), cache, ctypes.byref(plan), _stream(self.device)))
+        self._plan = plan
+
+    def shape(self):
+        g, o = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().usbf_batch_plan_shape(self._plan, ctypes.byref(g), ctypes.byref(o)))
+        return g.value, o.value
+
+    def run(self):
+        _check(lib().usbf_batch_run(self._plan, _stream(self.device)))
+        return self.images
+
+    def close(self):
+        if self._plan is not None and _lib is not None:
+            _lib.usbf_batch_plan_destroy(self._plan)
+        self._plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

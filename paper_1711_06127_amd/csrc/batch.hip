@@ -1,0 +1,302 @@
+// Batched pipeline over items of different sizes: one persistent delay-and-sum launch (work
+// units drawn from a device counter, most expensive items first), then each item's envelope
+// and log/scan-conversion epilogue, captured in a HIP graph; plus the autotuner that picks the
+// persistent launch shape by timing graph replays.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "das.h"
+
+namespace usbf {
+int envelope_enqueue(const float* in, int64_t n_rows, int n, float* env, float* row_max, hipStream_t s);
+int validate_scan(const usbf_scan* s);
+}  // namespace usbf
+
+using namespace usbf;
+
+struct usbf_batch_plan {
+  std::vector<usbf_batch_item> items;
+  BatchItemDev* d_items = nullptr;
+  int* d_counter = nullptr;
+  float* d_frame = nullptr;  // per-item frame maxima for the log compression (64 floats each)
+  int n_items = 0, total_units = 0, grid = 0, groups_per_cu = 2, cost_order = 1;
+  size_t lds = 0;
+  bool vec = true;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+constexpr int kFrameSlot = 64;
+
+bool envelope_length_ok(int n) {
+  int m = n;
+  for (int R : {2, 3, 5})
+    while (m % R == 0) m /= R;
+  return m == 1 && n >= 8 && n <= 2048;
+}
+
+void destroy(usbf_batch_plan* p) {
+  if (!p) return;
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->d_items) (void)hipFree(p->d_items);
+  if (p->d_counter) (void)hipFree(p->d_counter);
+  if (p->d_frame) (void)hipFree(p->d_frame);
+  delete p;
+}
+
+std::string arch_name() {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+  return std::string(prop.gcnArchName);
+}
+
+// signature of the batch: architecture + FNV-1a hash of every item's sizes, in order
+std::string batch_key(const usbf_batch_item* items, int n) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](int64_t v) {
+    for (int b = 0; b < 8; ++b) {
+      h ^= uint64_t((v >> (8 * b)) & 0xff);
+      h *= 1099511628211ull;
+    }
+  };
+  mix(n);
+  for (int i = 0; i < n; ++i) {
+    mix(items[i].geom.n_el);
+    mix(items[i].geom.n_lines);
+    mix(items[i].geom.lines_per_tx);
+    mix(items[i].rx.n_samples);
+    mix(items[i].rx.n_depth);
+  }
+  char buf[64];
+  snprintf(buf, sizeof buf, "%016llx", (unsigned long long)h);
+  std::string arch = arch_name();
+  for (char& c : arch)
+    if (c == '"' || c == '\\') c = '_';
+  return arch + "/" + buf;
+}
+
+// The cache is a flat JSON object: {"<key>": {"groups_per_cu": g, "cost_order": c, "ms": t}, ...}
+std::map<std::string, std::string> read_cache(const char* path) {
+  std::map<std::string, std::string> m;
+  if (!path) return m;
+  std::ifstream f(path);
+  if (!f) return m;
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string s = ss.str();
+  size_t pos = 0;
+  while ((pos = s.find('"', pos)) != std::string::npos) {
+    const size_t kend = s.find('"', pos + 1);
+    if (kend == std::string::npos) break;
+    const std::string key = s.substr(pos + 1, kend - pos - 1);
+    const size_t ob = s.find('{', kend), cb = s.find('}', kend);
+    if (ob == std::string::npos || cb == std::string::npos || ob > cb) break;
+    m[key] = s.substr(ob, cb - ob + 1);
+    pos = cb + 1;
+  }
+  return m;
+}
+
+int json_int(const std::string& obj, const char* name, int dflt) {
+  const std::string k = std::string("\"") + name + "\"";
+  const size_t p = obj.find(k);
+  if (p == std::string::npos) return dflt;
+  const size_t c = obj.find(':', p);
+  if (c == std::string::npos) return dflt;
+  return atoi(obj.c_str() + c + 1);
+}
+
+int write_cache(const char* path, const std::map<std::string, std::string>& m) {
+  std::ofstream f(path, std::ios::trunc);
+  if (!f) return fail(USBF_EINVAL, "cannot write tune cache %s", path);
+  f << "{\n";
+  size_t i = 0;
+  for (const auto& kv : m) f << "  \"" << kv.first << "\": " << kv.second << (++i < m.size() ? ",\n" : "\n");
+  f << "}\n";
+  return USBF_OK;
+}
+
+int make_plan(const usbf_batch_item* items, int n, int groups_per_cu, int cost_order, usbf_batch_plan** out,
+              hipStream_t user_stream) {
+  (void)user_stream;
+  USBF_REQUIRE(items && out, USBF_EINVAL, "null items or plan");
+  USBF_REQUIRE(n >= 1 && n <= 65536, USBF_EINVAL, "n_items %d out of range", n);
+  USBF_REQUIRE(groups_per_cu >= 1 && groups_per_cu <= 8, USBF_EINVAL, "groups per CU out of range");
+  std::vector<BatchItemDev> dev(n);
+  bool vec = true;
+  int max_el = 1;
+  for (int i = 0; i < n; ++i) {
+    const usbf_batch_item& it = items[i];
+    DasArgs a;
+    int st = make_das_args(&it.geom, &it.rx, &a);
+    if (st) return fail(st, "item %d: %s", i, usbf_last_error_detail());
+    USBF_REQUIRE(it.rf && it.lines && it.row_max && it.image, USBF_EINVAL, "item %d: null buffer", i);
+    st = validate_scan(&it.scan);
+    if (st) return fail(st, "item %d: %s", i, usbf_last_error_detail());
+    USBF_REQUIRE(it.scan.n_depth == it.rx.n_depth, USBF_ESHAPE, "item %d: scan and receive depth counts differ", i);
+    const int64_t scan_lines = int64_t(it.scan.n_u) * (it.scan.kind == 1 ? it.scan.n_v : 1);
+    USBF_REQUIRE(scan_lines == it.geom.n_lines, USBF_ESHAPE, "item %d: scan covers %lld lines, geometry %d", i,
+                 (long long)scan_lines, it.geom.n_lines);
+    USBF_REQUIRE(envelope_length_ok(it.rx.n_depth), USBF_EUNSUPPORTED, "item %d: n_depth %d", i, it.rx.n_depth);
+    USBF_REQUIRE(finite_pos(it.dyn_range_db), USBF_EINVAL, "item %d: dyn_range_db", i);
+    vec = vec && (it.rx.n_samples % 4 == 0) && ((reinterpret_cast<uintptr_t>(it.rf) & 7) == 0);
+    max_el = std::max(max_el, it.geom.n_el);
+    st = batch_item_setup(a, it.geom.lines_per_tx >= 4 ? 4 : 1, &dev[i]);
+    if (st) return fail(st, "item %d: %s", i, usbf_last_error_detail());
+    dev[i].rf = it.rf;
+    dev[i].out = it.lines;
+  }
+  const size_t lds = persistent_lds_bytes(max_el);
+  USBF_REQUIRE(lds <= 65536, USBF_EUNSUPPORTED, "items with %d elements exceed the tile LDS", max_el);
+  // unit order: most expensive units (most elements) first, stable
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  if (cost_order)
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return dev[x].a.n_el > dev[y].a.n_el; });
+  std::vector<BatchItemDev> table(n);
+  int64_t units = 0;
+  for (int k = 0; k < n; ++k) {
+    table[k] = dev[order[k]];
+    table[k].unit_begin = int(units);
+    units += table[k].n_units;
+  }
+  USBF_REQUIRE(units < (int64_t(1) << 30), USBF_EUNSUPPORTED, "too many work units");
+
+  usbf_batch_plan* p = new usbf_batch_plan();
+  p->items.assign(items, items + n);
+  p->n_items = n;
+  p->total_units = int(units);
+  p->groups_per_cu = groups_per_cu;
+  p->cost_order = cost_order;
+  p->lds = lds;
+  p->vec = vec;
+  int dev_id = 0, n_cu = 0;
+  if (hipGetDevice(&dev_id) != hipSuccess ||
+      hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev_id) != hipSuccess) {
+    destroy(p);
+    return fail(USBF_EDEVICE, "device query failed");
+  }
+  p->grid = std::max(1, std::min(n_cu * groups_per_cu, p->total_units));
+  if (hipMalloc(&p->d_items, sizeof(BatchItemDev) * n) != hipSuccess ||
+      hipMalloc(&p->d_counter, 256) != hipSuccess ||
+      hipMalloc(&p->d_frame, sizeof(float) * kFrameSlot * n) != hipSuccess ||
+      hipMemcpy(p->d_items, table.data(), sizeof(BatchItemDev) * n, hipMemcpyHostToDevice) != hipSuccess) {
+    destroy(p);
+    return fail(USBF_EDEVICE, "batch plan allocation failed");
+  }
+  // capture on a private stream (the caller's may be the legacy null stream)
+  hipStream_t cs;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+    destroy(p);
+    return fail(USBF_EDEVICE, "stream creation failed");
+  }
+  int st = USBF_OK;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) st = fail(USBF_EDEVICE, "capture");
+  if (!st) st = launch_persistent(p->d_items, n, p->total_units, p->d_counter, vec, p->grid, lds, cs);
+  for (int i = 0; i < n && !st; ++i) {
+    const usbf_batch_item& it = items[i];
+    st = envelope_enqueue(it.lines, it.geom.n_lines, it.rx.n_depth, it.lines, it.row_max, cs);
+    if (!st)
+      st = usbf_log_scan_convert(it.lines, it.row_max, 1, &it.scan, it.dyn_range_db, 0.0f, it.image,
+                                 p->d_frame + size_t(kFrameSlot) * i, sizeof(float) * kFrameSlot, cs);
+  }
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(cs, &g);
+  if (!st && ec != hipSuccess) st = fail(USBF_EDEVICE, "end capture: %s", hipGetErrorString(ec));
+  p->graph = g;
+  if (!st && hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess)
+    st = fail(USBF_EDEVICE, "graph instantiation failed");
+  (void)hipStreamDestroy(cs);
+  if (st) {
+    destroy(p);
+    return st;
+  }
+  *out = p;
+  return USBF_OK;
+}
+
+}  // namespace
+
+extern "C" int usbf_batch_plan_create(const usbf_batch_item* items, int32_t n_items, const char* tune_cache,
+                                      usbf_batch_plan** plan, hipStream_t stream) {
+  USBF_REQUIRE(items && plan, USBF_EINVAL, "null items or plan");
+  USBF_REQUIRE(n_items >= 1, USBF_EINVAL, "empty batch");
+  int gpc = 2, order = 1;
+  const auto cache = read_cache(tune_cache);
+  const auto it = cache.find(batch_key(items, n_items));
+  if (it != cache.end()) {
+    gpc = std::min(8, std::max(1, json_int(it->second, "groups_per_cu", gpc)));
+    order = json_int(it->second, "cost_order", order) ? 1 : 0;
+  }
+  return make_plan(items, n_items, gpc, order, plan, stream);
+}
+
+extern "C" int usbf_batch_run(usbf_batch_plan* plan, hipStream_t stream) {
+  USBF_REQUIRE(plan && plan->exec, USBF_EINVAL, "null plan");
+  const hipError_t e = hipGraphLaunch(plan->exec, stream);
+  if (e != hipSuccess) return fail(USBF_EDEVICE, "graph launch: %s", hipGetErrorString(e));
+  return USBF_OK;
+}
+
+extern "C" int usbf_batch_plan_destroy(usbf_batch_plan* plan) {
+  destroy(plan);
+  return USBF_OK;
+}
+
+extern "C" int usbf_batch_plan_shape(const usbf_batch_plan* plan, int32_t* groups_per_cu, int32_t* cost_order) {
+  USBF_REQUIRE(plan && groups_per_cu && cost_order, USBF_EINVAL, "null argument");
+  *groups_per_cu = plan->groups_per_cu;
+  *cost_order = plan->cost_order;
+  return USBF_OK;
+}
+
+extern "C" int usbf_autotune(const usbf_batch_item* items, int32_t n_items, const char* tune_cache,
+                             hipStream_t stream) {
+  USBF_REQUIRE(items && tune_cache, USBF_EINVAL, "null items or cache path");
+  float best_ms = 1e30f;
+  int best_g = 2, best_o = 1;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(USBF_EDEVICE, "event creation failed");
+  int st = USBF_OK;
+  for (int order = 1; order >= 0 && !st; --order) {
+    for (int g = 1; g <= 4 && !st; ++g) {
+      usbf_batch_plan* p = nullptr;
+      st = make_plan(items, n_items, g, order, &p, stream);
+      if (st) break;
+      for (int w = 0; w < 2 && !st; ++w) st = usbf_batch_run(p, stream);
+      const int reps = 5;
+      (void)hipEventRecord(e0, stream);
+      for (int r = 0; r < reps && !st; ++r) st = usbf_batch_run(p, stream);
+      (void)hipEventRecord(e1, stream);
+      float ms = 0.0f;
+      if (!st && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        st = fail(USBF_EDEVICE, "timing failed");
+      destroy(p);
+      if (!st && ms / reps < best_ms) {
+        best_ms = ms / reps;
+        best_g = g;
+        best_o = order;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st) return st;
+  auto cache = read_cache(tune_cache);
+  char val[160];
+  snprintf(val, sizeof val, "{\"groups_per_cu\": %d, \"cost_order\": %d, \"ms\": %.4f}", best_g, best_o, best_ms);
+  cache[batch_key(items, n_items)] = val;
+  return write_cache(tune_cache, cache);
+}

@@ -57,4 +57,7 @@ struct DasArgs {
 
 int make_das_args(const usbf_geometry* g, const usbf_rx* rx, DasArgs* a);
 
+// workspace of the learned-apodization network for n_pix pixels of M elements
+size_t net_ws_bytes(int64_t n_pix, int64_t M, bool train);
+
 }  // namespace usbf

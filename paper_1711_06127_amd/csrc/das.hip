@@ -18,6 +18,7 @@
 #include <climits>
 
 #include "common.h"
+#include "das.h"
 #include "tof.h"
 
 namespace usbf {
@@ -59,13 +60,6 @@ struct Shape {
   static constexpr int EC = EC0 < kMaxChunk ? (EC0 < 1 ? 1 : EC0) : kMaxChunk;
   static constexpr int BUFV = EC * SPAN;  // staging buffer length in frame vectors
   static constexpr int IPT = (EC * (SPAN / 4) + kDasThreads - 1) / kDasThreads;
-};
-
-struct TileArgs {
-  int span;      // staged samples per element (multiple of 4)
-  int ec;        // elements per chunk
-  int n_dtiles;  // depth tiles per line
-  int pshift;    // 1: windows split into even and odd samples (even depth_step), else 0
 };
 
 // LDS of one workgroup: two staging buffers, the per-(line, element) receive constants of the
@@ -230,23 +224,21 @@ __device__ inline void store_stage(const Prefetch<VEC, FS, IPT>& pf, const Items
   }
 }
 
-// Delay-and-sum for frames [frame0, frame0 + n_blocks * FB) of the batch.
+// Delay-and-sum of one tile -- lines [group G, group G + G) x depths [dt TD, dt TD + TD) --
+// for frames [frame0, frame0 + n_blocks * FB) of the batch.  Every lane of the workgroup
+// calls it with the same tile.
 template <bool VEC, int G, int FB, int FS>
-__global__ __launch_bounds__(kDasThreads) void das_tile_kernel(const int16_t* __restrict__ rf, int frame0,
-                                                               int n_blocks, DasArgs a, TileArgs ta,
-                                                               float* __restrict__ out) {
+__device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int frame0, int n_blocks, const DasArgs& a,
+                                         const TileArgs& ta, float* __restrict__ out, unsigned char* lds_raw,
+                                         int group, int dt) {
   using V = typename FVec<FS>::T;
   using SH = Shape<G, FS>;
   constexpr int TD = SH::TD;
   constexpr int NS = FB / FS;
   constexpr int IPT = SH::IPT;
-  extern __shared__ __align__(16) unsigned char lds_raw[];
   const TileLds<G, FS> t = carve<G, FS>(lds_raw, a.n_el);
 
   const int tid = threadIdx.x;
-  const uint32_t bid = xcd_swizzle(blockIdx.x, gridDim.x);
-  const int group = int(bid / ta.n_dtiles);
-  const int dt = int(bid % ta.n_dtiles);
   const int g = tid / TD;
   const int l0 = group * G;
   const int l = l0 + g;
@@ -459,6 +451,53 @@ __global__ __launch_bounds__(kDasThreads) void das_tile_kernel(const int16_t* __
   }
 }
 
+// One workgroup per tile; workgroup ids are remapped so that consecutive depth tiles of a line
+// group run on the same XCD (they share the edges of their channel-data windows in L2).
+template <bool VEC, int G, int FB, int FS>
+__global__ __launch_bounds__(kDasThreads) void das_tile_kernel(const int16_t* __restrict__ rf, int frame0,
+                                                               int n_blocks, DasArgs a, TileArgs ta,
+                                                               float* __restrict__ out) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const uint32_t bid = xcd_swizzle(blockIdx.x, gridDim.x);
+  das_tile<VEC, G, FB, FS>(rf, frame0, n_blocks, a, ta, out, lds_raw, int(bid / ta.n_dtiles),
+                           int(bid % ta.n_dtiles));
+}
+
+// Persistent delay-and-sum over a table of items of different sizes (one frame each): every
+// workgroup takes work units -- one tile of one item -- from a device counter until the counter
+// passes the total, so the grid drains once every unit has been taken.  Units are numbered
+// item by item, items ordered as the host chose (most expensive first).
+template <bool VEC>
+__global__ __launch_bounds__(kDasThreads) void das_persistent_kernel(const BatchItemDev* __restrict__ items,
+                                                                     int n_items, int total_units,
+                                                                     int* __restrict__ counter) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  __shared__ int s_unit;
+  for (;;) {
+    __syncthreads();  // the previous tile is done with LDS and s_unit
+    if (threadIdx.x == 0) s_unit = atomicAdd(counter, 1);
+    __syncthreads();
+    const int u = s_unit;
+    if (u >= total_units) break;
+    int lo = 0, hi = n_items - 1;  // last item whose first unit is <= u
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (items[mid].unit_begin <= u) lo = mid; else hi = mid - 1;
+    }
+    const BatchItemDev& it = items[lo];
+    const int local = u - it.unit_begin;
+    const int group = local / it.ta.n_dtiles, dt = local % it.ta.n_dtiles;
+    if (it.G == 4)
+      das_tile<VEC, 4, 1, 1>(it.rf, 0, 1, it.a, it.ta, it.out, lds_raw, group, dt);
+    else
+      das_tile<VEC, 1, 1, 1>(it.rf, 0, 1, it.a, it.ta, it.out, lds_raw, group, dt);
+  }
+}
+
+__global__ void reset_counter_kernel(int* counter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
+}
+
 __global__ void delay_index_kernel(DasArgs a, int32_t* __restrict__ i0, uint8_t* __restrict__ flags,
                                    float* __restrict__ phi) {
   const int64_t n = int64_t(a.n_lines) * a.n_depth * a.n_el;
@@ -535,6 +574,48 @@ static int launch_das_g(const int16_t* rf, int n_frames, const DasArgs& a, float
   run(2, [&](int f, int nb) { return launch_das<G, 2, 2>(rf, f, nb, a, out, s); });
   run(1, [&](int f, int nb) { return launch_das<G, 1, 1>(rf, f, nb, a, out, s); });
   return st;
+}
+
+template <int G>
+static TileArgs single_frame_tiles(const DasArgs& a) {
+  using SH = Shape<G, 1>;
+  TileArgs ta;
+  ta.span = (a.depth_step * SH::TD + kWindowMargin + 3) & ~3;
+  ta.ec = std::min(SH::EC, SH::BUFV / ta.span);
+  if (ta.ec < 1) {
+    ta.ec = 1;
+    ta.span = SH::BUFV & ~3;
+  }
+  ta.pshift = (a.depth_step % 2 == 0) ? 1 : 0;
+  ta.n_dtiles = (a.n_depth + SH::TD - 1) / SH::TD;
+  return ta;
+}
+
+int batch_item_setup(const DasArgs& a, int G, BatchItemDev* it) {
+  USBF_REQUIRE(G == 1 || G == 4, USBF_EUNSUPPORTED, "batched tiles group 1 or 4 lines");
+  it->a = a;
+  it->G = G;
+  it->ta = G == 4 ? single_frame_tiles<4>(a) : single_frame_tiles<1>(a);
+  const int64_t units = int64_t((a.n_lines + G - 1) / G) * it->ta.n_dtiles;
+  USBF_REQUIRE(units < (int64_t(1) << 30), USBF_EUNSUPPORTED, "too many tiles");
+  it->n_units = int(units);
+  return USBF_OK;
+}
+
+size_t persistent_lds_bytes(int max_n_el) {
+  return std::max(tile_lds_bytes<4, 1>(max_n_el), tile_lds_bytes<1, 1>(max_n_el));
+}
+
+int launch_persistent(const BatchItemDev* d_items, int n_items, int total_units, int* counter, bool vec, int grid,
+                      size_t lds, hipStream_t s) {
+  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, counter);
+  if (vec)
+    hipLaunchKernelGGL(das_persistent_kernel<true>, dim3(grid), dim3(kDasThreads), lds, s, d_items, n_items,
+                       total_units, counter);
+  else
+    hipLaunchKernelGGL(das_persistent_kernel<false>, dim3(grid), dim3(kDasThreads), lds, s, d_items, n_items,
+                       total_units, counter);
+  return check_launch("das_persistent_kernel");
 }
 
 int beamform_enqueue(const int16_t* rf, int32_t n_frames, const DasArgs& a, float* out, hipStream_t s) {

@@ -101,6 +101,10 @@ size_t usbf_workspace_bytes(int32_t op, int64_t n_frames, int64_t n_lines, int64
       // beamformed/envelope lines, per-row maxima, per-frame maxima
       return al(size_t(n_frames) * n_lines * n_depth * sizeof(float)) + al(size_t(n_frames) * n_lines * sizeof(float)) +
              al(size_t(n_frames) * sizeof(float));
+    case USBF_OP_APODNET:
+      return usbf::net_ws_bytes(n_frames, n_lines, false);
+    case USBF_OP_APODNET_TRAIN:
+      return usbf::net_ws_bytes(n_frames, n_lines, true);
     default:
       return 0;
   }

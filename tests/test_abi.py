@@ -139,3 +139,32 @@ def test_workspace_sizes(u):
     b = L.usbf_workspace_bytes(3, 32, 256, 2048)
     assert b >= 32 * 256 * 2048 * 4 + 32 * 256 * 4 + 32 * 4
     assert L.usbf_workspace_bytes(99, 1, 1, 1) == 0
+
+
+def test_batch_plan_rejects(u):
+    """Batch validation runs before any device call: every case fails with its status on a
+    machine without a GPU."""
+    L = u.lib()
+    plan = ctypes.c_void_p()
+    good = u.CBatchItem(FAKE, geom(u, n_lines=4), rx(u), scan(u, n_depth=32), 50.0, FAKE, FAKE, FAKE)
+    arr = (u.CBatchItem * 2)(good, good)
+    assert L.usbf_batch_plan_create(arr, 0, None, ctypes.byref(plan), None) == -1
+    assert L.usbf_batch_plan_create(None, 1, None, ctypes.byref(plan), None) == -1
+    assert L.usbf_batch_plan_create(arr, 1, None, None, None) == -1
+    bad = (u.CBatchItem * 2)(good, u.CBatchItem(FAKE, geom(u, n_lines=5), rx(u), scan(u, n_depth=32), 50.0,
+                                                 FAKE, FAKE, FAKE))
+    assert L.usbf_batch_plan_create(bad, 2, None, ctypes.byref(plan), None) == -2      # scan lines != n_lines
+    bad[1] = u.CBatchItem(FAKE, geom(u, n_lines=4), rx(u), scan(u, n_depth=31), 50.0, FAKE, FAKE, FAKE)
+    assert L.usbf_batch_plan_create(bad, 2, None, ctypes.byref(plan), None) == -2      # depth counts differ
+    bad[1] = u.CBatchItem(FAKE, geom(u, n_lines=4), rx(u), scan(u, n_depth=32), 0.0, FAKE, FAKE, FAKE)
+    assert L.usbf_batch_plan_create(bad, 2, None, ctypes.byref(plan), None) == -1      # dynamic range
+    bad[1] = u.CBatchItem(None, geom(u, n_lines=4), rx(u), scan(u, n_depth=32), 50.0, FAKE, FAKE, FAKE)
+    assert L.usbf_batch_plan_create(bad, 2, None, ctypes.byref(plan), None) == -1      # null rf
+    bad[1] = u.CBatchItem(FAKE, geom(u, n_lines=4), rx(u, n_depth=56, n_samples=200), scan(u, n_depth=56), 50.0,
+                          FAKE, FAKE, FAKE)
+    assert L.usbf_batch_plan_create(bad, 2, None, ctypes.byref(plan), None) == -3      # envelope length
+    assert L.usbf_batch_run(None, None) == -1
+    assert L.usbf_batch_plan_destroy(None) == 0
+    g, o = ctypes.c_int32(), ctypes.c_int32()
+    assert L.usbf_batch_plan_shape(None, ctypes.byref(g), ctypes.byref(o)) == -1
+    assert L.usbf_autotune(arr, 1, None, None) == -1

@@ -262,3 +262,60 @@ def test_point_targets_peak_on_their_pixels(usbf):
         win = env[max(l - 2, 0):l + 3, j - 20:j + 21]
         ll, jj = np.unravel_index(np.argmax(win), win.shape)
         assert (ll + max(l - 2, 0), jj + j - 20) == (l, j)
+
+
+# ------------------------------------------------------------------ delay-gather and minimum variance
+
+def test_delay_gather_matches_oracle(usbf):
+    g = synth.config_multiline_2d()
+    rf = sim(g, 3000, n_frames=2)
+    dg = usbf.DeviceGeometry(g)
+    rng = np.random.default_rng(0)
+    m = 3000
+    pix = np.stack([rng.integers(0, 2, m), rng.integers(0, g.n_lines, m), rng.integers(0, g.n_depth, m)], 1)
+    pix[:5] = [[0, 0, 0], [1, 255, 2047], [0, 128, 1], [1, 3, 1024], [0, 77, 2046]]
+    x = usbf.delay_gather(rf, dg, torch.as_tensor(pix, dtype=torch.int32).cuda()).cpu().numpy()
+    ref = oracle.delay_gather(g, rf.cpu().numpy(), pix)
+    assert np.abs(x - ref).max() <= TOL * np.abs(ref).max()
+
+
+def test_delay_gather_out_of_range_pixels_give_zeros(usbf):
+    g = synth.config_small_2d()
+    rf = sim(g, 3100)
+    dg = usbf.DeviceGeometry(g)
+    pix = torch.tensor([[0, 5, 100], [1, 5, 100], [0, 64, 0], [0, 0, 1024], [-1, 0, 0]], dtype=torch.int32).cuda()
+    x = usbf.delay_gather(rf, dg, pix).cpu().numpy()
+    assert np.abs(x[0]).max() > 0 and np.all(x[1:] == 0)
+
+
+def test_mv_weights_match_oracle(usbf):
+    """Binary32 covariance, binary64 Cholesky: weights within 1e-2 (relative 2-norm; the loaded
+    matrix has condition number <= 1 + L/loading = 3201) and outputs within 1e-3 of the
+    float64 oracle on the same binary32 inputs."""
+    from oracle import mv
+    g = synth.config_multiline_2d()
+    rf = sim(g, 3200)
+    dg = usbf.DeviceGeometry(g)
+    rng = np.random.default_rng(1)
+    m = 2000
+    pix = np.stack([np.zeros(m, int), rng.integers(0, g.n_lines, m), rng.integers(200, g.n_depth, m)], 1)
+    x = usbf.delay_gather(rf, dg, torch.as_tensor(pix, dtype=torch.int32).cuda())
+    wf, y = usbf.mv_weights(x, 32, 1e-2)
+    xr = x.cpu().numpy().astype(np.float64)
+    wf_ref, y_ref, _ = mv.mv_weights(xr, 32, 1e-2)
+    wf = wf.cpu().numpy()
+    rel = np.linalg.norm(wf - wf_ref, axis=1) / np.linalg.norm(wf_ref, axis=1)
+    assert np.median(rel) < 1e-3 and rel.max() < 1e-2
+    assert np.abs(y.cpu().numpy() - y_ref).max() <= 1e-3 * np.abs(y_ref).max()
+    np.testing.assert_allclose(wf.sum(1), 1.0, atol=1e-5)
+
+
+def test_mv_closed_forms_on_gpu(usbf):
+    """Coherent data -> uniform subaperture weights; a nulled interferer (cf. the oracle pins)."""
+    M = 128
+    x = torch.full((3, M), 2.5, device="cuda")
+    wf, y = usbf.mv_weights(x, 32, 1e-2)
+    np.testing.assert_allclose(y.cpu().numpy(), 2.5, rtol=1e-5)
+    K = 97
+    count = np.array([min(e, 31) - max(0, e - K + 1) + 1 for e in range(M)])
+    np.testing.assert_allclose(wf.cpu().numpy(), np.broadcast_to(count / (K * 32), (3, M)), atol=1e-6)

@@ -1,0 +1,91 @@
+"""Pins of the minimum-variance oracle: the distortionless constraint, optimality (KKT),
+closed forms for coherent and heavily loaded data, and interference suppression."""
+import numpy as np
+import pytest
+
+from oracle import mv
+
+
+def test_constraint_and_full_aperture_sum():
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal((20, 128))
+    wf, y, w = mv.mv_weights(x)
+    np.testing.assert_allclose(w.sum(1), 1.0, atol=1e-12)
+    np.testing.assert_allclose(wf.sum(1), 1.0, atol=1e-12)
+    np.testing.assert_allclose(y, (wf * x).sum(1), atol=1e-12)
+
+
+def test_kkt_and_optimality():
+    """A w = lambda 1 with lambda = 1 / (1^T A^-1 1), and no feasible perturbation lowers w^T A w."""
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((5, 128)) * np.linspace(1, 3, 128)
+    A = mv.loaded(mv.covariance(x, 32), 1e-2)
+    wf, y, w = mv.mv_weights(x)
+    for p in range(5):
+        Aw = A[p] @ w[p]
+        np.testing.assert_allclose(Aw, Aw.mean(), rtol=1e-10)
+        lam = 1.0 / np.linalg.solve(A[p], np.ones(32)).sum()
+        assert Aw.mean() == pytest.approx(lam, rel=1e-10)
+        base = w[p] @ A[p] @ w[p]
+        for _ in range(20):
+            d = rng.standard_normal(32)
+            d -= d.mean()                       # keeps 1^T (w + d) = 1
+            u = w[p] + 1e-2 * d
+            assert u @ A[p] @ u >= base
+
+
+def test_covariance_definition_identities():
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal((3, 40))
+    R = mv.covariance(x, 8)
+    np.testing.assert_allclose(R, np.transpose(R, (0, 2, 1)), atol=0)
+    K = 40 - 8 + 1
+    tr = np.array([sum(np.sum(x[p, l:l + 8] ** 2) for l in range(K)) / K for p in range(3)])
+    np.testing.assert_allclose(np.trace(R, axis1=1, axis2=2), tr, rtol=1e-12)
+    assert np.all(np.linalg.eigvalsh(R) > -1e-12)
+
+
+def test_coherent_signal_gives_uniform_weights():
+    """Identical samples on every element: R = c^2 1 1^T, whose loaded inverse maps 1 to a
+    multiple of 1, so w = 1/L and the output is c."""
+    c = 3.5
+    x = np.full((2, 128), c)
+    wf, y, w = mv.mv_weights(x)
+    np.testing.assert_allclose(w, 1.0 / 32, atol=1e-14)
+    np.testing.assert_allclose(y, c, rtol=1e-12)
+
+
+def test_heavy_loading_tends_to_uniform_subaperture_weights():
+    """Loading -> infinity: w -> 1/L and w_full -> the triangular-edged average of the K
+    overlapping subapertures (count of subapertures containing e) / (K L)."""
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((4, 128))
+    wf, y, w = mv.mv_weights(x, loading=1e9)
+    np.testing.assert_allclose(w, 1.0 / 32, atol=1e-9)
+    K = 97
+    count = np.array([min(e, 31) - max(0, e - K + 1) + 1 for e in range(128)])
+    np.testing.assert_allclose(wf, np.broadcast_to(count / (K * 32), wf.shape), atol=1e-9)
+
+
+def test_interference_is_suppressed():
+    """Broadside signal (equal on all elements) plus a 20x stronger interferer with a linear
+    phase ramp across the aperture: MV keeps the signal (distortionless) and nulls the
+    interferer, which uniform subaperture weights let through."""
+    M, L = 128, 32
+    e = np.arange(M)
+    rng = np.random.default_rng(4)
+    n = 64
+    s = rng.standard_normal(n)
+    phase = rng.uniform(0, 2 * np.pi, n)
+    x = s[:, None] + 20.0 * np.cos(2 * np.pi * 0.11 * e[None, :] + phase[:, None])
+    wf, y, w = mv.mv_weights(x, L=L, loading=1e-3)
+    y_uniform = (mv.expand(np.full((n, L), 1.0 / L), M) * x).sum(1)
+    err_mv, err_uniform = np.median(np.abs(y - s)), np.median(np.abs(y_uniform - s))
+    assert err_uniform > 0.02          # the interferer leaks through fixed weights ...
+    assert err_mv < 0.05 * err_uniform  # ... and is nulled by the adaptive ones
+
+
+def test_all_zero_pixel_gets_uniform_weights():
+    wf, y, w = mv.mv_weights(np.zeros((2, 128)))
+    np.testing.assert_allclose(w, 1.0 / 32, atol=1e-15)
+    assert np.all(y == 0)
