@@ -37,6 +37,49 @@ def kernel_hash(paths):
     return h.hexdigest()[:16]
 
 
+CALIB_BYTES = 1 << 30
+DAS_SOURCES = ["paper_1711_06127_amd/csrc/das.hip", "paper_1711_06127_amd/csrc/das.h",
+               "paper_1711_06127_amd/csrc/tof.h", "paper_1711_06127_amd/csrc/common.h"]
+
+
+def _counter_rows(path, counter):
+    """(kernel name, value) per dispatch of one counter from a rocprofv3 counter_collection.csv."""
+    import csv
+    out = {}
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] != counter:
+                continue
+            key = int(r["Dispatch_Id"]) if "Dispatch_Id" in r else len(out)
+            name, val = r["Kernel_Name"], float(r["Counter_Value"])
+            out[key] = (name, out.get(key, (name, 0.0))[1] + val)
+    return [out[k] for k in sorted(out)]
+
+
+def write_traffic(args):
+    """HBM bytes per DAS launch, each counter scaled so that the 1 GiB copy reads and writes
+    exactly 1 GiB."""
+    res = {}
+    for counter, path in (("FETCH_SIZE", args.traffic_from[0]), ("WRITE_SIZE", args.traffic_from[1])):
+        rows = _counter_rows(path, counter)
+        das = [v for n, v in rows if "das_tile_kernel" in n]
+        copies = [v for n, v in rows if ("copyBuffer" in n or "elementwise" in n) and v * 1024 > 0.5 * CALIB_BYTES]
+        if not das or not copies:
+            raise SystemExit(f"{path}: no das_tile_kernel or calibration copy dispatch for {counter}")
+        scale = CALIB_BYTES / (copies[-1] * 1024.0)
+        res[counter] = {"raw_kib_per_launch": sum(das) / len(das), "copy_raw_kib": copies[-1], "scale": scale,
+                        "bytes_per_launch": sum(das) / len(das) * 1024.0 * scale, "launches": len(das)}
+    entry = {"sources": DAS_SOURCES, "source_hash": kernel_hash(DAS_SOURCES), "units": args.frames or 32,
+             "bytes_per_launch": res["FETCH_SIZE"]["bytes_per_launch"] + res["WRITE_SIZE"]["bytes_per_launch"],
+             "counters": res, "command": args.traffic_command}
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    d = json.load(open(path)) if os.path.exists(path) else {}
+    d["das"] = entry
+    with open(path, "w") as f:
+        json.dump(d, f, indent=1)
+    print(json.dumps(entry, indent=1))
+
+
 def traffic_from_profile(name, per_launch_units):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it still matches
     the kernel source; otherwise None."""
@@ -60,9 +103,10 @@ WORKLOADS = {
                                      "64 x 1024 lines -> 256 x 256 B-mode"),
     "volume": ("config_volume_3d", 1, "matrix 32 x 32 el, 1024 steered tx/lines over +-30 deg, 2000 int16 samples "
                                       "@ 20 MHz, 32 x 32 x 1000 lines -> 128^3 B-mode volume"),
-    "stream": ("stream_mix", 16, "uneven stream, seeded 70/30 mix of linear frames (64/128/192 el, 2048/4096 "
-                                 "samples, 1 or 4 lines per transmit) and matrix volumes (16x16 el / 1000 samples, "
-                                 "32x32 el / 2000 samples), one persistent graph-captured launch per batch"),
+    "stream": ("stream_mix", 100, "uneven stream of 100 items, seeded 70/30 mix of linear frames (64/128/192 el, "
+                                  "2048..4096 samples, n_el/2 transmits x 4 lines, 512^2 images) and matrix volumes "
+                                  "(16x16 or 32x32 el, 1000..2000 samples, 32x32 lines, 128^3 volumes), one "
+                                  "persistent graph-captured delay-and-sum launch per batch"),
 }
 
 
@@ -112,7 +156,15 @@ def main():
     ap.add_argument("--unique-frames", type=int, default=8)
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="after the timed steps, copy a 1 GiB buffer (the reference kernel for HBM counters)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="no GPU: turn two rocprofv3 counter collections (FETCH_SIZE, WRITE_SIZE) of a "
+                         "--calib-copy run into profiles/traffic.json")
+    ap.add_argument("--traffic-command", default="", help="the profiled command, recorded with the figures")
     args = ap.parse_args()
+    if args.traffic_from:
+        return write_traffic(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this library runs on one GPU; multi-GPU runs are not part of it "
                                    f"(asked for --gpus {args.gpus})"}))
@@ -204,6 +256,12 @@ def main():
                      "traffic": traffic_from_profile("das", F), "kernel": "das (delay-and-sum)",
                      "algorithmic_bytes": rf_bytes + out_bytes},
     }
+    if args.calib_copy:
+        src = torch.empty(CALIB_BYTES, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
     if not args.no_cpu:
         rf_h = rf.cpu().numpy()
         result["cpu_baseline"] = cpu_baseline(g, rf_h, args.cpu_budget)
@@ -223,13 +281,22 @@ def run_stream(args, dev):
 
     n_items = args.frames or WORKLOADS["stream"][1]
     gs = synth.stream_mix(seed=0, n_items=n_items)
-    sims = {}
     t = time.perf_counter()
+    # one simulated acquisition per probe at its longest record; each item takes the first
+    # n_samples of it, as its own copy (separate acquisitions)
+    base = {}
     for g in gs:
-        if id(g) not in sims:
-            sims[id(g)] = (make_batch(g, 1, 1, dev, volume=g.scan.kind == 1)[0], u.DeviceGeometry(g, dev))
-    # every item gets its own copy of the channel data, as separate acquisitions would
-    items = [(sims[id(g)][0].clone(), sims[id(g)][1]) for g in gs]
+        key = (g.array_dims, g.n_el)
+        if key in base:
+            continue
+        if g.array_dims == 1:
+            gl = synth.linear_2d("sim", n_el=g.n_el, n_tx=g.n_tx, lines_per_tx=4, line_pitch=0.15e-3, n_samples=4096)
+            base[key] = make_batch(gl, 1, 1, dev)[0]
+        else:
+            gm = synth.matrix_3d("sim", n_side=int(round(g.n_el ** 0.5)), n_samples=2000)
+            base[key] = make_batch(gm, 1, 1, dev, volume=True)[0]
+    items = [(base[(g.array_dims, g.n_el)][..., :g.n_samples].contiguous(), u.DeviceGeometry(g, dev)) for g in gs]
+    base.clear()
     torch.cuda.synchronize()
     log(f"stream: {len(gs)} items, {sum(x[0].numel() for x in items) * 2 / 2**30:.2f} GiB int16, "
         f"generated in {time.perf_counter() - t:.1f} s")
@@ -272,7 +339,8 @@ def run_stream(args, dev):
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": WORKLOADS["stream"][2], "items": len(gs),
-                   "kinds": sorted({g.name for g in gs}), "dyn_range_db": 50},
+                   "linear_frames": sum(g.array_dims == 1 for g in gs),
+                   "matrix_volumes": sum(g.array_dims == 2 for g in gs), "dyn_range_db": 50},
         "items_per_s": len(gs) / (step_ms * 1e-3),
         "graph_ms": graph_ms,
         "autotuned_shape": {"groups_per_cu": shape[0], "cost_order": shape[1]},
@@ -288,8 +356,8 @@ def run_stream(args, dev):
         done = 0
         n = 0
         for (rf, dg), g in zip(items, gs):
-            if g.scan.kind == 1 and g.n_el > 256:
-                continue  # a 32x32 volume alone takes minutes in the oracle
+            if g.scan.kind == 1:
+                continue  # a single volume takes minutes in the oracle
             y = oracle.das(g, rf.unsqueeze(0).cpu().numpy())
             (oracle.bmode_3d if g.scan.kind == 1 else oracle.bmode_2d)(y[0], g.scan, 50.0)
             done += g.n_lines * g.n_depth * g.n_el
@@ -299,7 +367,7 @@ def run_stream(args, dev):
         dt = time.perf_counter() - t0
         result["cpu_baseline"] = {"value": done / dt, "unit": "pixel·channel samples/s",
                                   "cores": oracle.num_threads(), "kind": "oracle",
-                                  "sample": f"{n} item(s) of the stream (2D frames and 16x16 volumes) through "
+                                  "sample": f"{n} linear frame(s) of the stream through "
                                             f"the float64 oracle, {dt:.1f} s"}
     plan.close()
     print(json.dumps(result), flush=True)

@@ -149,7 +149,7 @@ int usbf_beamform(const int16_t* rf, int32_t n_frames, const usbf_geometry* geom
  *   H[k] = 0 otherwise (circular, no padding).
  *   in, env  float [n_rows][n]  (in == env allowed: in place)
  *   row_max  float [n_rows] maximum of each env row, or NULL.
- * n must be 2^a 3^b 5^c with 8 <= n <= 2048.
+ * 8 <= n <= 2048 and every prime factor of n at most 31 (e.g. 1000, 1024, 1408, 1664, 950).
  */
 int usbf_envelope(const float* in, int64_t n_rows, int32_t n, float* env, float* row_max,
                   hipStream_t stream);

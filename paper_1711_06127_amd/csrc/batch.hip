@@ -37,13 +37,6 @@ namespace {
 
 constexpr int kFrameSlot = 64;
 
-bool envelope_length_ok(int n) {
-  int m = n;
-  for (int R : {2, 3, 5})
-    while (m % R == 0) m /= R;
-  return m == 1 && n >= 8 && n <= 2048;
-}
-
 void destroy(usbf_batch_plan* p) {
   if (!p) return;
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
@@ -135,7 +128,7 @@ int make_plan(const usbf_batch_item* items, int n, int groups_per_cu, int cost_o
   USBF_REQUIRE(groups_per_cu >= 1 && groups_per_cu <= 8, USBF_EINVAL, "groups per CU out of range");
   std::vector<BatchItemDev> dev(n);
   bool vec = true;
-  int max_el = 1;
+  int max_el[2] = {0, 0};  // largest element count among 1-line and 4-line items
   for (int i = 0; i < n; ++i) {
     const usbf_batch_item& it = items[i];
     DasArgs a;
@@ -151,14 +144,16 @@ int make_plan(const usbf_batch_item* items, int n, int groups_per_cu, int cost_o
     USBF_REQUIRE(envelope_length_ok(it.rx.n_depth), USBF_EUNSUPPORTED, "item %d: n_depth %d", i, it.rx.n_depth);
     USBF_REQUIRE(finite_pos(it.dyn_range_db), USBF_EINVAL, "item %d: dyn_range_db", i);
     vec = vec && (it.rx.n_samples % 4 == 0) && ((reinterpret_cast<uintptr_t>(it.rf) & 7) == 0);
-    max_el = std::max(max_el, it.geom.n_el);
-    st = batch_item_setup(a, it.geom.lines_per_tx >= 4 ? 4 : 1, &dev[i]);
+    const int G = it.geom.lines_per_tx >= 4 ? 4 : 1;
+    max_el[G == 4] = std::max(max_el[G == 4], it.geom.n_el);
+    st = batch_item_setup(a, G, &dev[i]);
     if (st) return fail(st, "item %d: %s", i, usbf_last_error_detail());
     dev[i].rf = it.rf;
     dev[i].out = it.lines;
   }
-  const size_t lds = persistent_lds_bytes(max_el);
-  USBF_REQUIRE(lds <= 65536, USBF_EUNSUPPORTED, "items with %d elements exceed the tile LDS", max_el);
+  const size_t lds = persistent_lds_bytes(max_el[0], max_el[1]);
+  USBF_REQUIRE(lds <= 65536, USBF_EUNSUPPORTED, "items with %d / %d elements (1- / 4-line tiles) exceed the tile LDS",
+               max_el[0], max_el[1]);
   // unit order: most expensive units (most elements) first, stable
   std::vector<int> order(n);
   for (int i = 0; i < n; ++i) order[i] = i;

@@ -57,6 +57,9 @@ struct DasArgs {
 
 int make_das_args(const usbf_geometry* g, const usbf_rx* rx, DasArgs* a);
 
+// envelope lengths the FFT supports: 8 <= n <= 2048, every prime factor <= 31
+bool envelope_length_ok(int n);
+
 // workspace of the learned-apodization network for n_pix pixels of M elements
 size_t net_ws_bytes(int64_t n_pix, int64_t M, bool train);
 

@@ -25,8 +25,9 @@ struct BatchItemDev {
 
 // Fills the tiling of an item for tiles of G lines (G = 1 or 4), one frame per block.
 int batch_item_setup(const DasArgs& a, int G, BatchItemDev* it);
-// LDS bytes the persistent kernel needs for items of up to max_n_el elements.
-size_t persistent_lds_bytes(int max_n_el);
+// LDS bytes the persistent kernel needs for 1-line tiles of up to max_n_el_g1 elements and
+// 4-line tiles of up to max_n_el_g4 elements (0: no such tiles).
+size_t persistent_lds_bytes(int max_n_el_g1, int max_n_el_g4);
 int launch_persistent(const BatchItemDev* d_items, int n_items, int total_units, int* counter, bool vec, int grid,
                       size_t lds, hipStream_t s);
 

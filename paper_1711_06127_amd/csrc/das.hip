@@ -602,8 +602,11 @@ int batch_item_setup(const DasArgs& a, int G, BatchItemDev* it) {
   return USBF_OK;
 }
 
-size_t persistent_lds_bytes(int max_n_el) {
-  return std::max(tile_lds_bytes<4, 1>(max_n_el), tile_lds_bytes<1, 1>(max_n_el));
+size_t persistent_lds_bytes(int max_n_el_g1, int max_n_el_g4) {
+  size_t b = 0;
+  if (max_n_el_g1 > 0) b = std::max(b, tile_lds_bytes<1, 1>(max_n_el_g1));
+  if (max_n_el_g4 > 0) b = std::max(b, tile_lds_bytes<4, 1>(max_n_el_g4));
+  return b;
 }
 
 int launch_persistent(const BatchItemDev* d_items, int n_items, int total_units, int* counter, bool vec, int grid,

@@ -3,7 +3,8 @@
 // positive and removing the negative frequencies.
 //
 // One workgroup owns a row at a time (grid-stride over rows so the twiddle table is built
-// once per workgroup) and runs a mixed-radix (2, 3, 4, 5) self-sorting Stockham FFT in LDS.
+// once per workgroup) and runs a mixed-radix self-sorting Stockham FFT in LDS: radix 2, 3, 4,
+// 5 butterflies, and the plain DFT for prime factors 7 ... 31.
 // The inverse transform is done as a forward transform of the conjugate: the magnitude of
 // conj(FFT(conj(X))) / n needs no final conjugation.
 #include "common.h"
@@ -75,6 +76,22 @@ __device__ inline void dft5(c32* v) {
   v[3] = csub(p2, q2);
 }
 
+// Forward DFT of prime size R by its definition, y_k = sum_m v_m e^{-2 pi i m k / R}; the
+// roots come from the n-point table (tw[q * n / R] = e^{-2 pi i q / R}).
+template <int R>
+__device__ inline void dft_prime(c32* v, const c32* __restrict__ tw, int tw_r) {
+  c32 out[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    c32 acc = v[0];
+#pragma unroll
+    for (int m = 1; m < R; ++m) acc = cadd(acc, cmul(v[m], tw[((m * k) % R) * tw_r]));
+    out[k] = acc;
+  }
+#pragma unroll
+  for (int k = 0; k < R; ++k) v[k] = out[k];
+}
+
 template <int R>
 __device__ inline void stage(const c32* __restrict__ a, c32* __restrict__ b, const c32* __restrict__ tw, int n, int ns) {
   const int m = n / R;
@@ -90,6 +107,7 @@ __device__ inline void stage(const c32* __restrict__ a, c32* __restrict__ b, con
     if constexpr (R == 3) dft3(v);
     if constexpr (R == 4) dft4(v);
     if constexpr (R == 5) dft5(v);
+    if constexpr (R > 5) dft_prime<R>(v, tw, m);
     const int o = (j / ns) * ns * R + k;
 #pragma unroll
     for (int r = 0; r < R; ++r) b[o + r * ns] = v[r];
@@ -104,14 +122,20 @@ __device__ inline int fft_lds(c32* buf0, c32* buf1, const c32* tw, const FftPlan
   int cur = 0;
   for (int s = 0; s < P.n_stages; ++s) {
     const int R = P.radix[s];
-    if (R == 4)
-      stage<4>(a, b, tw, P.n, ns);
-    else if (R == 2)
-      stage<2>(a, b, tw, P.n, ns);
-    else if (R == 3)
-      stage<3>(a, b, tw, P.n, ns);
-    else
-      stage<5>(a, b, tw, P.n, ns);
+    switch (R) {
+      case 4: stage<4>(a, b, tw, P.n, ns); break;
+      case 2: stage<2>(a, b, tw, P.n, ns); break;
+      case 3: stage<3>(a, b, tw, P.n, ns); break;
+      case 5: stage<5>(a, b, tw, P.n, ns); break;
+      case 7: stage<7>(a, b, tw, P.n, ns); break;
+      case 11: stage<11>(a, b, tw, P.n, ns); break;
+      case 13: stage<13>(a, b, tw, P.n, ns); break;
+      case 17: stage<17>(a, b, tw, P.n, ns); break;
+      case 19: stage<19>(a, b, tw, P.n, ns); break;
+      case 23: stage<23>(a, b, tw, P.n, ns); break;
+      case 29: stage<29>(a, b, tw, P.n, ns); break;
+      default: stage<31>(a, b, tw, P.n, ns); break;
+    }
     __syncthreads();
     c32* t = a;
     a = b;
@@ -183,7 +207,7 @@ int make_fft_plan(int n, FftPlan* P) {
   P->n = n;
   P->n_stages = 0;
   int m = n;
-  const int order[4] = {4, 2, 3, 5};
+  const int order[12] = {4, 2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31};
   for (int R : order) {
     while (m % R == 0) {
       if (P->n_stages >= kMaxStages) return USBF_EUNSUPPORTED;
@@ -194,9 +218,14 @@ int make_fft_plan(int n, FftPlan* P) {
   return m == 1 ? USBF_OK : USBF_EUNSUPPORTED;
 }
 
+bool envelope_length_ok(int n) {
+  FftPlan P;
+  return n >= 8 && n <= kMaxEnvelopeLength && make_fft_plan(n, &P) == USBF_OK;
+}
+
 int envelope_enqueue(const float* in, int64_t n_rows, int n, float* env, float* row_max, hipStream_t s) {
   FftPlan P;
-  USBF_REQUIRE(make_fft_plan(n, &P) == USBF_OK, USBF_EUNSUPPORTED, "envelope length %d is not 2^a 3^b 5^c", n);
+  USBF_REQUIRE(make_fft_plan(n, &P) == USBF_OK, USBF_EUNSUPPORTED, "envelope length %d has a prime factor above 31", n);
   const int64_t blocks = std::min<int64_t>(n_rows, 8192);
   const size_t lds = size_t(3) * n * sizeof(c32);
   hipLaunchKernelGGL(envelope_kernel, dim3(unsigned(blocks)), dim3(kEnvThreads), lds, s, in, n_rows, P, env,

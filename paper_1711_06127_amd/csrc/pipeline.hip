@@ -35,13 +35,8 @@ extern "C" int usbf_bmode(const int16_t* rf, int32_t n_frames, const usbf_geomet
   float* row_max = reinterpret_cast<float*>(w + al(size_t(rows) * a.n_depth * sizeof(float)));
   float* frame_ws = reinterpret_cast<float*>(reinterpret_cast<char*>(row_max) + al(size_t(rows) * sizeof(float)));
   // validate the envelope length and the scan grid before anything is enqueued
-  {
-    int m = a.n_depth;
-    for (int R : {2, 3, 5})
-      while (m % R == 0) m /= R;
-    USBF_REQUIRE(m == 1 && a.n_depth >= 8 && a.n_depth <= 2048, USBF_EUNSUPPORTED,
-                 "n_depth %d is not 2^a 3^b 5^c in 8..2048", a.n_depth);
-  }
+  USBF_REQUIRE(envelope_length_ok(a.n_depth), USBF_EUNSUPPORTED,
+               "n_depth %d: not in 8..2048 or a prime factor above 31", a.n_depth);
   st = validate_scan(scan);
   if (st) return st;
   st = beamform_enqueue(rf, n_frames, a, lines, stream);

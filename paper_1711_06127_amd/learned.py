@@ -1,0 +1,234 @@
+"""Learned adaptive apodization on top of the delay-and-sum path.
+
+A small 1D convolutional network (4 layers, 32 channels, kernel 5) maps the delayed channel
+samples of one pixel to one weight per element.  It is trained to reproduce minimum-variance
+(Capon) weights, which the library computes on the GPU for the same pixels (spatial smoothing
+over subapertures, diagonal loading, binary64 Cholesky); inference replaces the covariance
+estimate and the solve by one network evaluation.  Plain delay-and-sum stays the fallback for
+any pixel whose weights are not finite.  Every numeric step -- gathering the delayed samples,
+the minimum-variance solve, the network's forward and backward passes, the Adam update, the
+weighted sum, envelope and compression -- runs in the library's HIP kernels; this module only
+schedules them and measures the resulting images.
+
+Image measures: contrast-to-noise ratio of anechoic cysts, |mu_in - mu_out| / sqrt(var_in +
+var_out) of the envelope, and the lateral -6 dB width of point-target responses.
+
+Run ``python -m paper_1711_06127_amd.learned`` on a GPU to train and compare the three
+beamformers on held-out phantoms (prints one JSON line).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import time
+
+import numpy as np
+import torch
+
+from . import (ApodNet, DeviceGeometry, beamform, beamform_weighted, delay_gather, envelope, mv_weights)
+
+SUBAPERTURE = 32
+LOADING = 1e-2
+
+
+def init_params(seed: int = 0, n_el: int = 128) -> dict:
+    """He-uniform initialisation of the network; the output bias starts at 1 / n_el so the
+    untrained network gives roughly uniform weights."""
+    rng = np.random.default_rng(seed)
+
+    def u(shape, fan_in, scale=1.0):
+        b = np.sqrt(6.0 / fan_in) * scale
+        return rng.uniform(-b, b, shape).astype(np.float32)
+
+    return {"W1": u((32, 1, 5), 5), "b1": np.zeros(32, np.float32),
+            "W2": u((32, 32, 5), 160), "b2": np.zeros(32, np.float32),
+            "W3": u((32, 32, 5), 160), "b3": np.zeros(32, np.float32),
+            "W4": u((1, 32, 5), 160, 0.1), "b4": np.full(1, 1.0 / n_el, np.float32)}
+
+
+def frame_pixels(n_lines: int, n_depth: int, frame: int = 0, device="cuda") -> torch.Tensor:
+    """Every (frame, line, depth) pixel of one frame, line-major, int32 [n_lines * n_depth, 3]."""
+    l = torch.arange(n_lines, dtype=torch.int32, device=device).repeat_interleave(n_depth)
+    j = torch.arange(n_depth, dtype=torch.int32, device=device).repeat(n_lines)
+    f = torch.full_like(l, frame)
+    return torch.stack([f, l, j], dim=1).contiguous()
+
+
+def random_pixels(gen: torch.Generator, n: int, n_frames: int, n_lines: int, n_depth: int, j_min: int,
+                  device="cuda") -> torch.Tensor:
+    f = torch.randint(0, n_frames, (n,), generator=gen, device=device, dtype=torch.int32)
+    l = torch.randint(0, n_lines, (n,), generator=gen, device=device, dtype=torch.int32)
+    j = torch.randint(j_min, n_depth, (n,), generator=gen, device=device, dtype=torch.int32)
+    return torch.stack([f, l, j], dim=1).contiguous()
+
+
+class LearnedApodization:
+    """Network state plus the training loop on minimum-variance targets."""
+
+    def __init__(self, n_el: int = 128, seed: int = 0, params: dict | None = None, device="cuda"):
+        self.n_el = n_el
+        self.net = ApodNet(params if params is not None else init_params(seed, n_el), device)
+        self.device = torch.device(device)
+
+    def train(self, rf: torch.Tensor, dg: DeviceGeometry, steps: int, batch: int = 4096, lr: float = 1e-3,
+              seed: int = 0, j_min: int = 0, log_every: int = 0) -> list:
+        """Adam steps on random pixels of the frames rf [F, n_tx, n_el, S]; the targets are
+        minimum-variance weights computed for the same pixels.  Returns the loss history."""
+        gen = torch.Generator(device=self.device)
+        gen.manual_seed(seed)
+        loss = torch.zeros(1, device=self.device)
+        hist = []
+        for s in range(steps):
+            pix = random_pixels(gen, batch, rf.shape[0], dg.n_lines, dg.n_depth, j_min, self.device)
+            x = delay_gather(rf, dg, pix)
+            target, _ = mv_weights(x, SUBAPERTURE, LOADING)
+            cur_lr = lr * (0.1 if s >= int(0.8 * steps) else 1.0)
+            self.net.train_step(x, target, cur_lr, loss)
+            if log_every and (s % log_every == 0 or s == steps - 1):
+                hist.append((s, float(loss.item())))
+        return hist
+
+    def weights(self, x: torch.Tensor) -> torch.Tensor:
+        return self.net.forward(x)
+
+
+def beamform_lines(rf: torch.Tensor, dg: DeviceGeometry, method: str, model: LearnedApodization | None = None,
+                   chunk: int = 65536) -> torch.Tensor:
+    """Beamformed lines [n_lines, n_depth] of one frame rf [n_tx, n_el, S] by 'das' (the
+    library's delay-and-sum), 'mv' (minimum variance) or 'learned' (network weights, with the
+    delay-and-sum value as the fallback)."""
+    das = beamform(rf.unsqueeze(0) if rf.dim() == 3 else rf, dg)[0]
+    if method == "das":
+        return das
+    pix_all = frame_pixels(dg.n_lines, dg.n_depth, 0, rf.device)
+    out = torch.empty(dg.n_lines * dg.n_depth, dtype=torch.float32, device=rf.device)
+    fb = das.reshape(-1)
+    for c0 in range(0, pix_all.shape[0], chunk):
+        pix = pix_all[c0:c0 + chunk]
+        x = delay_gather(rf, dg, pix)
+        if method == "mv":
+            _, y = mv_weights(x, SUBAPERTURE, LOADING, want_weights=False)
+        elif method == "learned":
+            y = beamform_weighted(x, model.weights(x), fb[c0:c0 + chunk].contiguous())
+        else:
+            raise ValueError(method)
+        out[c0:c0 + pix.shape[0]] = y
+    return out.reshape(dg.n_lines, dg.n_depth)
+
+
+def frame_envelope(lines: torch.Tensor) -> np.ndarray:
+    env = envelope(lines.unsqueeze(0).contiguous())[0].cpu().numpy().astype(np.float64)
+    return env
+
+
+def psf_widths(env: np.ndarray, line_x: np.ndarray, targets) -> np.ndarray:
+    """Lateral -6 dB width (metres) of each point target (line, depth) on envelope lines
+    [n_lines, n_depth]; the lateral profile takes the maximum over +-2 depth samples."""
+    widths = []
+    n_lines = env.shape[0]
+    for (l0, j0) in targets:
+        prof = env[:, max(0, j0 - 2): j0 + 3].max(axis=1)
+        lo, hi = max(0, l0 - 2), min(n_lines, l0 + 3)
+        lp = lo + int(np.argmax(prof[lo:hi]))
+        half = 0.5 * prof[lp]
+        # walk out from the peak to the first sample below half amplitude, interpolate linearly
+        def cross(step):
+            k = lp
+            while 0 <= k + step < n_lines and prof[k + step] >= half:
+                k += step
+            if not 0 <= k + step < n_lines:
+                return float(line_x[k])
+            a, b = prof[k], prof[k + step]
+            t = (a - half) / (a - b)
+            return float(line_x[k] + t * (line_x[k + step] - line_x[k]))
+        widths.append(abs(cross(1) - cross(-1)))
+    return np.array(widths)
+
+
+def cnr(env: np.ndarray, line_x: np.ndarray, depth_z: np.ndarray, cysts) -> np.ndarray:
+    """Contrast-to-noise ratio of each cyst (cx, cz, r): inside 0.8 r against the ring 1.2 r..1.8 r."""
+    X, Z = np.meshgrid(line_x, depth_z, indexing="ij")
+    out = []
+    for (cx, cz, r) in cysts:
+        d2 = (X - cx) ** 2 + (Z - cz) ** 2
+        inside = env[d2 <= (0.8 * r) ** 2]
+        ring = env[(d2 >= (1.2 * r) ** 2) & (d2 <= (1.8 * r) ** 2)]
+        out.append(abs(inside.mean() - ring.mean()) / np.sqrt(inside.var() + ring.var()))
+    return np.array(out)
+
+
+def _sim(g, seed, cysts=(), n_speckle=5000, device="cuda"):
+    import synth  # seeded input generation (synthetic phantoms)
+    pos, amp, lj = synth.phantom.phantom_2d(g, seed, n_speckle=n_speckle, cysts=cysts)
+    return synth.rfsim.simulate_frame(g, pos, amp, seed, device=device).contiguous(), lj
+
+
+def evaluate(model: LearnedApodization, g, dg: DeviceGeometry, seed: int = 900) -> dict:
+    """CNR on a cyst phantom and -6 dB widths on a sparse point phantom for DAS, MV and the
+    network, plus the GPU time of the MV and network weight paths for one frame."""
+    lx = g.line_origin[:, 0].astype(np.float64)
+    z = np.array([g.depth_of(j) for j in range(g.n_depth)], dtype=np.float64)
+    span = lx[-1] - lx[0]
+    cysts = [(-0.2 * span, 0.3 * z[-1], 3e-3), (0.2 * span, 0.5 * z[-1], 4e-3)]
+    rf_c, _ = _sim(g, seed, cysts=cysts)
+    rf_p, lj = _sim(g, seed + 1, n_speckle=200)
+    res = {}
+    for m in ("das", "mv", "learned"):
+        env_c = frame_envelope(beamform_lines(rf_c, dg, m, model))
+        env_p = frame_envelope(beamform_lines(rf_p, dg, m, model))
+        res[m] = {"cnr": cnr(env_c, lx, z, cysts).tolist(),
+                  "psf_width_mm": (psf_widths(env_p, lx, lj) * 1e3).tolist()}
+    # weight-path timing on one full frame (gather excluded: both need it)
+    pix = frame_pixels(dg.n_lines, dg.n_depth, 0, rf_c.device)[:262144]
+    x = delay_gather(rf_c, dg, pix)
+    for name, fn in (("mv", lambda: mv_weights(x, SUBAPERTURE, LOADING)),
+                     ("learned", lambda: model.weights(x))):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        res[name]["weights_ms_per_262144_px"] = e0.elapsed_time(e1) / 5
+    return res
+
+
+def main():
+    import synth
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--frames", type=int, default=16)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--save", default="")
+    args = ap.parse_args()
+    g = synth.config_multiline_2d()
+    dg = DeviceGeometry(g)
+    rng = np.random.default_rng(1)
+    lx = g.line_origin[:, 0].astype(np.float64)
+    zmax = g.depth_of(g.n_depth - 1)
+    frames = []
+    t = time.perf_counter()
+    for f in range(args.frames):
+        cysts = [(rng.uniform(0.8 * lx[0], 0.8 * lx[-1]), rng.uniform(0.15, 0.85) * zmax, rng.uniform(2e-3, 5e-3))
+                 for _ in range(2)]
+        frames.append(_sim(g, 100 + f, cysts=cysts)[0])
+    rf = torch.stack(frames).contiguous()
+    torch.cuda.synchronize()
+    t_sim = time.perf_counter() - t
+    model = LearnedApodization(g.n_el, seed=0)
+    t = time.perf_counter()
+    hist = model.train(rf, dg, args.steps, args.batch, args.lr, log_every=max(1, args.steps // 20))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t
+    res = evaluate(model, g, dg)
+    if args.save:
+        np.savez(args.save, **model.net.params())
+    print(json.dumps({"train_frames": args.frames, "steps": args.steps, "batch": args.batch, "sim_s": t_sim,
+                      "train_s": t_train, "loss": hist, "eval": res}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

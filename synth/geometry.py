@@ -232,37 +232,27 @@ def config_tiny(n_el=4, n_tx=2, lines_per_tx=3, n_samples=32, depth_step=2, wind
     return g
 
 
-def stream_mix(seed: int = 0, n_items: int = 16, frac_2d: float = 0.7) -> list:
-    """An uneven acquisition stream in a seeded random order: about frac_2d linear-array frames
-    (64 / 128 / 192 elements, 2048 or 4096 samples, 64 transmits with 1 or 4 receive lines) and
-    the rest matrix-array volumes (16 x 16 elements with 16 x 16 lines and 1000 samples, or
-    32 x 32 elements with 32 x 32 lines and 2000 samples).  Geometries of one kind are shared
-    objects, so equal items can reuse simulated channel data."""
+def stream_mix(seed: int = 0, n_items: int = 100, frac_2d: float = 0.7) -> list:
+    """An uneven acquisition stream in a seeded random order: round(frac_2d * n_items)
+    linear-array frames and the rest matrix-array volumes.
+
+    Linear: n_el uniform in {64, 128, 192}, n_samples uniform in {2048, 2304, ..., 4096},
+    n_el / 2 transmits with 4 receive lines each (lines at half the element pitch), 5 MHz,
+    40 MHz sampling, 512 x 512 image.  Matrix: 16 x 16 or 32 x 32 elements with equal
+    probability, n_samples uniform in {1000, 1100, ..., 2000}, 32 x 32 steered lines with one
+    transmit each, 3.5 MHz, 20 MHz sampling, 128^3 volume."""
     rng = np.random.default_rng(seed)
-    cache = {}
-
-    def get(key, make):
-        if key not in cache:
-            cache[key] = make()
-        return cache[key]
-
+    n2 = int(round(frac_2d * n_items))
+    kinds = rng.permutation(np.array([2] * n2 + [3] * (n_items - n2)))
     out = []
-    for _ in range(n_items):
-        if rng.random() < frac_2d:
+    for k in kinds:
+        if k == 2:
             n_el = int(rng.choice([64, 128, 192]))
-            n_s = int(rng.choice([2048, 4096]))
-            lpt = int(rng.choice([1, 4]))
-            key = ("2d", n_el, n_s, lpt)
-            side = 256 if n_s == 2048 else 512
-            out.append(get(key, lambda: linear_2d(f"linear{n_el}_64tx_x{lpt}_{n_s}", n_el=n_el, n_tx=64,
-                                                  lines_per_tx=lpt, line_pitch=n_el * 0.3e-3 / (64 * lpt), n_samples=n_s,
-                                                  scan_n=(side, side))))
+            n_s = int(rng.choice(np.arange(2048, 4097, 256)))
+            out.append(linear_2d(f"linear{n_el}_{n_el // 2}tx_x4_{n_s}", n_el=n_el, n_tx=n_el // 2, lines_per_tx=4,
+                                 line_pitch=0.15e-3, n_samples=n_s, scan_n=(512, 512)))
         else:
-            small = bool(rng.random() < 0.5)
-            key = ("3d", small)
-            if small:
-                out.append(get(key, lambda: matrix_3d("matrix16x16_256tx_1000", n_side=16, n_samples=1000,
-                                                      n_lines_side=16, scan_n=64)))
-            else:
-                out.append(get(key, lambda: matrix_3d("matrix32x32_1024tx_2000", n_side=32, n_samples=2000)))
+            side = int(rng.choice([16, 32]))
+            n_s = int(rng.choice(np.arange(1000, 2001, 100)))
+            out.append(matrix_3d(f"matrix{side}x{side}_1024tx_{n_s}", n_side=side, n_samples=n_s))
     return out

@@ -85,7 +85,7 @@ def test_beamform_rejects_bad_geometry_and_sizes(u):
 def test_envelope_and_log_reject(u):
     L = u.lib()
     assert L.usbf_envelope(FAKE, 4, 4, FAKE, None, None) == -3            # too short
-    assert L.usbf_envelope(FAKE, 4, 7 * 11 * 8, FAKE, None, None) == -3   # 7 and 11 unsupported
+    assert L.usbf_envelope(FAKE, 4, 37 * 8, FAKE, None, None) == -3       # prime factor 37 > 31
     assert L.usbf_envelope(FAKE, 4, 8192, FAKE, None, None) == -3          # too long
     assert L.usbf_envelope(None, 4, 64, FAKE, None, None) == -1
     assert L.usbf_envelope(FAKE, 0, 64, FAKE, None, None) == -1
@@ -126,9 +126,9 @@ def test_bmode_rejects_inconsistent_shapes(u):
                         None) == -2
     assert L.usbf_bmode(FAKE, 1, ctypes.byref(g), ctypes.byref(r), ctypes.byref(s), 50.0, FAKE, FAKE, ws - 1,
                         None) == -4
-    r7 = rx(u, n_depth=7 * 8, n_samples=200)
-    s7 = scan(u, n_depth=56)
-    ws7 = u.lib().usbf_workspace_bytes(3, 1, 4, 56)
+    r7 = rx(u, n_depth=37 * 2, n_samples=200)
+    s7 = scan(u, n_depth=74)
+    ws7 = u.lib().usbf_workspace_bytes(3, 1, 4, 74)
     assert L.usbf_bmode(FAKE, 1, ctypes.byref(g), ctypes.byref(r7), ctypes.byref(s7), 50.0, FAKE, FAKE, ws7,
                         None) == -3
 
@@ -160,7 +160,7 @@ def test_batch_plan_rejects(u):
     assert L.usbf_batch_plan_create(bad, 2, None, ctypes.byref(plan), None) == -1      # dynamic range
     bad[1] = u.CBatchItem(None, geom(u, n_lines=4), rx(u), scan(u, n_depth=32), 50.0, FAKE, FAKE, FAKE)
     assert L.usbf_batch_plan_create(bad, 2, None, ctypes.byref(plan), None) == -1      # null rf
-    bad[1] = u.CBatchItem(FAKE, geom(u, n_lines=4), rx(u, n_depth=56, n_samples=200), scan(u, n_depth=56), 50.0,
+    bad[1] = u.CBatchItem(FAKE, geom(u, n_lines=4), rx(u, n_depth=74, n_samples=200), scan(u, n_depth=74), 50.0,
                           FAKE, FAKE, FAKE)
     assert L.usbf_batch_plan_create(bad, 2, None, ctypes.byref(plan), None) == -3      # envelope length
     assert L.usbf_batch_run(None, None) == -1
