@@ -16,6 +16,7 @@
 // A (pixel, element) pair whose samples fall outside the staged window (only for unusual
 // geometry) reads global memory directly, so the result never depends on the tiling.
 #include <climits>
+#include <type_traits>
 
 #include "common.h"
 #include "das.h"
@@ -224,6 +225,15 @@ __device__ inline void store_stage(const Prefetch<VEC, FS, IPT>& pf, const Items
   }
 }
 
+// f(integral_constant<int, 0>) ... f(integral_constant<int, N - 1>)
+template <int N, int I = 0, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<N, I + 1>(f);
+  }
+}
+
 // Delay-and-sum of one tile -- lines [group G, group G + G) x depths [dt TD, dt TD + TD) --
 // for frames [frame0, frame0 + n_blocks * FB) of the batch.  Every lane of the workgroup
 // calls it with the same tile.
@@ -332,7 +342,80 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
   };
   const uint32_t fbytes = uint32_t(std::min<uint64_t>(frame_stride * sizeof(int16_t), 0xffffffffull));
 
-  Prefetch<VEC, FS, IPT> pf;
+  // Channel-data steps -- one FS-frame stage of one chunk -- run in order q = 0, 1, ...  Step q
+  // is summed from LDS buffer q & 1 while the loads of step q + 2 are in flight into register
+  // set q & 1 (which step q's data left at the end of step q - 1); at the end of step q the
+  // data of step q + 1 (register set (q + 1) & 1) is converted into LDS buffer (q + 1) & 1.
+  // Two steps of loads are thus in flight behind every sum.  With an even number of stages
+  // per chunk the parities follow the stage index; with one stage per chunk they follow the
+  // chunk ordinal, and the chunk loop is unrolled by two so that they stay compile-time.
+  static_assert(NS == 1 || NS % 2 == 0, "stages per chunk must be 1 or even");
+  Prefetch<VEC, FS, IPT> pf[2];
+  const bool stage_any = t_grp >= 0;
+
+  struct Taps {
+    int off0[SH::EC], off1[SH::EC];
+    float w0[SH::EC], w1[SH::EC];
+    uint32_t slow;
+  };
+  // taps of this lane's pixel for chunk c, shared by every frame; a tap that contributes
+  // nothing, or whose samples are not staged, reads the zero vector
+  auto make_taps = [&](int c, float& den) {
+    Taps T;
+    T.slow = 0u;
+    const int e0 = c * ta.ec;
+#pragma unroll
+    for (int k = 0; k < SH::EC; ++k) {
+      T.off0[k] = T.off1[k] = ZERO;
+      T.w0[k] = T.w1[k] = 0.0f;
+      if (k >= ta.ec) continue;
+      const int e = min(e0 + k, a.n_el - 1);
+      const float4 E4 = geo[e];
+      const ElemGeom E{E4.x, E4.y, E4.z, E4.w};
+      const bool act = lane_ok && e0 + k < a.n_el && in_aperture(a, E, r);
+      if (!__any(act)) continue;  // no lane of the wave needs this element
+      const float w = act ? apod_weight(a.window, a.array_dims, E.dx, E.dy, inv_w) : 0.0f;
+      den += w;
+      const Tap tp = fast_tap(a, b, dtx, E.A, E.B, r, r2, rr);
+      const bool ok = act && tp.i0 >= 0 && tp.i0 <= S - 2;
+      const float wp = w * tp.phi;
+      T.w1[k] = ok ? wp : 0.0f;
+      T.w0[k] = ok ? w - wp : 0.0f;
+      const int2 wd = t.wnd[e];
+      const int rel = tp.i0 - wd.x;
+      const bool in_win = on_grp && (t.flg[e] & 2) && rel >= 0 && tp.i0 + 1 <= wd.y && rel + 1 < ta.span;
+      const int wbase = k * ta.span;
+      const int p0 = ta.pshift ? ((rel & 1) * half + (rel >> 1)) : rel;
+      const int p1 = ta.pshift ? (((rel + 1) & 1) * half + ((rel + 1) >> 1)) : rel + 1;
+      T.off0[k] = (ok && in_win) ? wbase + p0 : ZERO;
+      T.off1[k] = (ok && in_win) ? wbase + p1 : ZERO;
+      T.slow |= (ok && !in_win) ? (1u << k) : 0u;
+    }
+    return T;
+  };
+  // taps outside the staged windows: read global memory
+  auto slow_taps = [&](const Taps& T, int c, int fb, float* acc) {
+    const int e0 = c * ta.ec;
+    for (int k = 0; k < ta.ec; ++k) {
+      if (!(T.slow & (1u << k))) continue;
+      const float4 E4 = geo[e0 + k];
+      const Tap tp = fast_tap(a, b, dtx, E4.x, E4.y, r, r2, rr);
+      const int16_t* p = own_block + size_t(e0 + k) * S + tp.i0;
+      float sw0 = 0.0f, sw1 = 0.0f;
+#pragma unroll
+      for (int kk = 0; kk < SH::EC; ++kk)
+        if (kk == k) {
+          sw0 = T.w0[kk];
+          sw1 = T.w1[kk];
+        }
+#pragma unroll
+      for (int f = 0; f < FB; ++f) {
+        const int16_t* q = p + size_t(fb + f) * frame_stride;
+        acc[f] = __builtin_fmaf(sw0, float(q[0]), __builtin_fmaf(sw1, float(q[1]), acc[f]));
+      }
+    }
+  };
+
   for (int blk = 0; blk < n_blocks; ++blk) {
     const int fb = frame0 + blk * FB;
     const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(grp_block + size_t(fb) * frame_stride);
@@ -340,105 +423,95 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
 #pragma unroll
     for (int f = 0; f < FB; ++f) acc[f] = 0.0f;
     float den = 0.0f;
-    int cur = 0;
     int c = next_chunk(-1);
-    const bool stage_any = t_grp >= 0;
     Items<IPT> items = chunk_items<VEC, G, FS, IPT>(t, ta, a, c < n_chunks && stage_any ? c : -1);
-    issue_stage<VEC, FS, IPT>(pf, items, rsrc, 0u, fbytes, S);
-    store_stage<VEC, G, FS, IPT>(pf, items, t.win, ta.span, ta.pshift);
-    __syncthreads();
-    while (c < n_chunks) {
-      const int e0 = c * ta.ec;
-      const int cn = next_chunk(c);
-      const Items<IPT> next_items =
-          chunk_items<VEC, G, FS, IPT>(t, ta, a, cn < n_chunks && stage_any ? cn : -1);
-      // taps of this lane's pixel for the chunk's elements, shared by every frame; a tap that
-      // contributes nothing, or whose samples are not staged, reads the zero vector
-      int off0[SH::EC], off1[SH::EC];
-      float w0[SH::EC], w1[SH::EC];
-      uint32_t slow = 0u;
+    // sum one stage (frames s FS .. s FS + FS - 1 of the block) from LDS buffer `buf`
+    auto sum_stage = [&](const Taps& T, int buf, auto s_) {
+      constexpr int s = decltype(s_)::value;
+      const V* w = t.win + buf * SH::BUFV;
 #pragma unroll
       for (int k = 0; k < SH::EC; ++k) {
-        off0[k] = off1[k] = ZERO;
-        w0[k] = w1[k] = 0.0f;
-        if (k >= ta.ec) continue;
-        const int e = min(e0 + k, a.n_el - 1);
-        const float4 E4 = geo[e];
-        const ElemGeom E{E4.x, E4.y, E4.z, E4.w};
-        const bool act = lane_ok && e0 + k < a.n_el && in_aperture(a, E, r);
-        if (!__any(act)) continue;  // no lane of the wave needs this element
-        const float w = act ? apod_weight(a.window, a.array_dims, E.dx, E.dy, inv_w) : 0.0f;
-        den += w;
-        const Tap tp = fast_tap(a, b, dtx, E.A, E.B, r, r2, rr);
-        const bool ok = act && tp.i0 >= 0 && tp.i0 <= S - 2;
-        const float wp = w * tp.phi;
-        w1[k] = ok ? wp : 0.0f;
-        w0[k] = ok ? w - wp : 0.0f;
-        const int2 wd = t.wnd[e];
-        const int rel = tp.i0 - wd.x;
-        const bool in_win = on_grp && (t.flg[e] & 2) && rel >= 0 && tp.i0 + 1 <= wd.y && rel + 1 < ta.span;
-        const int wbase = k * ta.span;
-        const int p0 = ta.pshift ? ((rel & 1) * half + (rel >> 1)) : rel;
-        const int p1 = ta.pshift ? (((rel + 1) & 1) * half + ((rel + 1) >> 1)) : rel + 1;
-        off0[k] = (ok && in_win) ? wbase + p0 : ZERO;
-        off1[k] = (ok && in_win) ? wbase + p1 : ZERO;
-        slow |= (ok && !in_win) ? (1u << k) : 0u;
+        // the zero vector sits after both buffers: index relative to this buffer
+        const int i0 = T.off0[k] == ZERO ? ZERO - buf * SH::BUFV : T.off0[k];
+        const int i1 = T.off1[k] == ZERO ? ZERO - buf * SH::BUFV : T.off1[k];
+        const V x0 = w[i0];
+        const V x1 = w[i1];
+#pragma unroll
+        for (int f = 0; f < FS; ++f)
+          acc[s * FS + f] = __builtin_fmaf(T.w0[k], FVec<FS>::get(x0, f),
+                                           __builtin_fmaf(T.w1[k], FVec<FS>::get(x1, f), acc[s * FS + f]));
       }
-      // keep the scheduler from interleaving the tap set-up with the frame stages (it would
-      // hoist LDS reads across it and run out of registers)
-      __builtin_amdgcn_sched_barrier(0);
+      // pin this stage's sums here: otherwise the accumulation may be sunk below later stages,
+      // keeping every stage's LDS reads alive at once
 #pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        const int buf = (NS % 2 == 0) ? (s & 1) : cur;
-        // prefetch the next step: this chunk's next frame stage, or the next chunk's first
-        const bool last = (s + 1 == NS);
-        const bool has_next = last ? (cn < n_chunks && stage_any) : stage_any;
-        const Items<IPT>& nit = last ? next_items : items;
-        if (has_next) issue_stage<VEC, FS, IPT>(pf, nit, rsrc, last ? 0u : uint32_t((s + 1) * FS) * fbytes, fbytes, S);
-        const V* w = t.win + buf * SH::BUFV;
-#pragma unroll
-        for (int k = 0; k < SH::EC; ++k) {
-          // the zero vector sits after both buffers: index relative to this buffer
-          const int i0 = off0[k] == ZERO ? ZERO - buf * SH::BUFV : off0[k];
-          const int i1 = off1[k] == ZERO ? ZERO - buf * SH::BUFV : off1[k];
-          const V x0 = w[i0];
-          const V x1 = w[i1];
-#pragma unroll
-          for (int f = 0; f < FS; ++f)
-            acc[s * FS + f] = __builtin_fmaf(w0[k], FVec<FS>::get(x0, f),
-                                             __builtin_fmaf(w1[k], FVec<FS>::get(x1, f), acc[s * FS + f]));
-        }
-        // pin this stage's sums here: otherwise the accumulation may be sunk below later stages,
-        // keeping every stage's LDS reads alive at once
-#pragma unroll
-        for (int f = 0; f < FS; ++f) asm volatile("" : "+v"(acc[s * FS + f]));
+      for (int f = 0; f < FS; ++f) asm volatile("" : "+v"(acc[s * FS + f]));
+    };
+
+    if constexpr (NS == 1) {
+      int cn = c < n_chunks ? next_chunk(c) : n_chunks;
+      Items<IPT> items_n = chunk_items<VEC, G, FS, IPT>(t, ta, a, cn < n_chunks && stage_any ? cn : -1);
+      issue_stage<VEC, FS, IPT>(pf[0], items, rsrc, 0u, fbytes, S);
+      store_stage<VEC, G, FS, IPT>(pf[0], items, t.win, ta.span, ta.pshift);
+      issue_stage<VEC, FS, IPT>(pf[1], items_n, rsrc, 0u, fbytes, S);
+      __syncthreads();
+      // chunk c sits in LDS buffer P, chunk cn is in flight into register set P ^ 1
+      auto body = [&](auto P_) {
+        constexpr int P = decltype(P_)::value;
+        const int cnn = cn < n_chunks ? next_chunk(cn) : n_chunks;
+        const Items<IPT> items_nn =
+            chunk_items<VEC, G, FS, IPT>(t, ta, a, cnn < n_chunks && stage_any ? cnn : -1);
+        if (cnn < n_chunks && stage_any) issue_stage<VEC, FS, IPT>(pf[P], items_nn, rsrc, 0u, fbytes, S);
+        const Taps T = make_taps(c, den);
+        // keep the scheduler from interleaving the tap set-up with the sums (it would hoist
+        // LDS reads across it and run out of registers)
         __builtin_amdgcn_sched_barrier(0);
-        if (has_next) store_stage<VEC, G, FS, IPT>(pf, nit, t.win + (buf ^ 1) * SH::BUFV, ta.span, ta.pshift);
+        sum_stage(T, P, std::integral_constant<int, 0>{});
+        __builtin_amdgcn_sched_barrier(0);
+        if (cn < n_chunks && stage_any)
+          store_stage<VEC, G, FS, IPT>(pf[P ^ 1], items_n, t.win + (P ^ 1) * SH::BUFV, ta.span, ta.pshift);
         __syncthreads();
-        if (NS % 2 != 0) cur ^= 1;
+        if (T.slow) slow_taps(T, c, fb, acc);
+        c = cn;
+        cn = cnn;
+        items_n = items_nn;
+      };
+      while (c < n_chunks) {
+        body(std::integral_constant<int, 0>{});
+        if (c >= n_chunks) break;
+        body(std::integral_constant<int, 1>{});
       }
-      if (slow) {  // taps outside the staged windows: read global memory
-        for (int k = 0; k < ta.ec; ++k) {
-          if (!(slow & (1u << k))) continue;
-          const float4 E4 = geo[e0 + k];
-          const Tap tp = fast_tap(a, b, dtx, E4.x, E4.y, r, r2, rr);
-          const int16_t* p = own_block + size_t(e0 + k) * S + tp.i0;
-          float sw0 = 0.0f, sw1 = 0.0f;
-#pragma unroll
-          for (int kk = 0; kk < SH::EC; ++kk)
-            if (kk == k) {
-              sw0 = w0[kk];
-              sw1 = w1[kk];
-            }
-#pragma unroll
-          for (int f = 0; f < FB; ++f) {
-            const int16_t* q = p + size_t(fb + f) * frame_stride;
-            acc[f] = __builtin_fmaf(sw0, float(q[0]), __builtin_fmaf(sw1, float(q[1]), acc[f]));
-          }
-        }
+    } else {
+      issue_stage<VEC, FS, IPT>(pf[0], items, rsrc, 0u, fbytes, S);
+      store_stage<VEC, G, FS, IPT>(pf[0], items, t.win, ta.span, ta.pshift);
+      issue_stage<VEC, FS, IPT>(pf[1], items, rsrc, uint32_t(FS) * fbytes, fbytes, S);
+      __syncthreads();
+      while (c < n_chunks) {
+        const int cn = next_chunk(c);
+        const Items<IPT> next_items =
+            chunk_items<VEC, G, FS, IPT>(t, ta, a, cn < n_chunks && stage_any ? cn : -1);
+        const Taps T = make_taps(c, den);
+        __builtin_amdgcn_sched_barrier(0);
+        auto step = [&](auto s_) {
+          constexpr int s = decltype(s_)::value;
+          constexpr bool wrap = s + 2 >= NS;  // step q + 2 is in the next chunk
+          constexpr bool last = s + 1 == NS;  // step q + 1 is in the next chunk
+          const bool has_ahead = wrap ? (cn < n_chunks && stage_any) : stage_any;
+          if (has_ahead)
+            issue_stage<VEC, FS, IPT>(pf[s & 1], wrap ? next_items : items, rsrc,
+                                      uint32_t(((s + 2) % NS) * FS) * fbytes, fbytes, S);
+          sum_stage(T, s & 1, s_);
+          __builtin_amdgcn_sched_barrier(0);
+          const bool has_next = last ? (cn < n_chunks && stage_any) : stage_any;
+          if (has_next)
+            store_stage<VEC, G, FS, IPT>(pf[(s + 1) & 1], last ? next_items : items,
+                                         t.win + ((s + 1) & 1) * SH::BUFV, ta.span, ta.pshift);
+          __syncthreads();
+        };
+        static_for<NS>(step);
+        if (T.slow) slow_taps(T, c, fb, acc);
+        items = next_items;
+        c = cn;
       }
-      items = next_items;
-      c = cn;
     }
     if (pix_ok) {
       const float inv = den > 0.0f ? 1.0f / den : 0.0f;

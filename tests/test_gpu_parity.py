@@ -80,7 +80,7 @@ def test_beamform_small_frame_matches_oracle(usbf):
     assert rel_err(y.cpu().numpy(), ref) <= TOL
 
 
-@pytest.mark.parametrize("n_frames", [1, 3, 5, 33])
+@pytest.mark.parametrize("n_frames", [1, 3, 5, 29, 33])
 def test_beamform_multiline_frames(usbf, n_frames):
     """Frame blocking (1, 2, 4 ... 32 frames per pass plus a ragged remainder) on the multi-line
     geometry; sampled pixels of every frame against the oracle."""
@@ -96,6 +96,22 @@ def test_beamform_multiline_frames(usbf, n_frames):
     ref = oracle.das(g, rf.cpu().numpy(), pix)
     got = y[pix[:, 0], pix[:, 1], pix[:, 2]]
     assert rel_err(got, ref) <= TOL
+
+
+def test_beamform_small_geometry_frame_blocks(usbf):
+    """One line per transmit with 37 frames (blocks of 32 + 4 + 1) against the oracle on
+    sampled pixels of every frame."""
+    g = synth.config_small_2d()
+    base = sim(g, 2500, n_frames=2)
+    rf = base[torch.arange(37) % 2].clone()
+    rf[2:] = torch.roll(rf[2:], shifts=3, dims=-1)
+    dg = usbf.DeviceGeometry(g)
+    y = usbf.beamform(rf, dg).cpu().numpy()
+    rng = np.random.default_rng(37)
+    m = 4000
+    pix = np.stack([rng.integers(0, 37, m), rng.integers(0, g.n_lines, m), rng.integers(0, g.n_depth, m)], 1)
+    ref = oracle.das(g, rf.cpu().numpy(), pix)
+    assert rel_err(y[pix[:, 0], pix[:, 1], pix[:, 2]], ref) <= TOL
 
 
 def test_beamform_volume_subset(usbf):
