@@ -32,8 +32,9 @@ LOADING = 1e-2
 
 
 def init_params(seed: int = 0, n_el: int = 128) -> dict:
-    """He-uniform initialisation of the network; the output bias starts at 1 / n_el so the
-    untrained network gives roughly uniform weights."""
+    """He-uniform initialisation of the hidden layers; the output layer starts near zero
+    (1e-3 of its He bound) and its bias at 1 / n_el, so the untrained network gives almost
+    exactly uniform weights and training starts from the uniform-weight loss."""
     rng = np.random.default_rng(seed)
 
     def u(shape, fan_in, scale=1.0):
@@ -43,7 +44,7 @@ def init_params(seed: int = 0, n_el: int = 128) -> dict:
     return {"W1": u((32, 1, 5), 5), "b1": np.zeros(32, np.float32),
             "W2": u((32, 32, 5), 160), "b2": np.zeros(32, np.float32),
             "W3": u((32, 32, 5), 160), "b3": np.zeros(32, np.float32),
-            "W4": u((1, 32, 5), 160, 0.1), "b4": np.full(1, 1.0 / n_el, np.float32)}
+            "W4": u((1, 32, 5), 160, 1e-3), "b4": np.full(1, 1.0 / n_el, np.float32)}
 
 
 def frame_pixels(n_lines: int, n_depth: int, frame: int = 0, device="cuda") -> torch.Tensor:

@@ -50,4 +50,4 @@ def test_pixel_lists():
 def test_initial_network_is_near_uniform():
     p = L.init_params(0, 128)
     assert p["b4"][0] == np.float32(1 / 128)
-    assert np.abs(p["W4"]).max() <= 0.1 * np.sqrt(6 / 160) + 1e-7
+    assert np.abs(p["W4"]).max() <= 1e-3 * np.sqrt(6 / 160) + 1e-9
