@@ -241,7 +241,9 @@ int usbf_mv_weights(const float* x, int32_t n_pix, int32_t n_el, int32_t subap, 
  *   params  float [10657] = W1[32][1][5] b1[32] W2[32][32][5] b2[32] W3[32][32][5] b3[32]
  *           W4[1][32][5] b4[1] (device), copied in by usbf_apodnet_init (moments reset).
  *   x, w, w_target  float [n_pix][n_el], n_el a multiple of 32 in 32..256 (LDS-resident rows).
- *   ws      workspace of usbf_workspace_bytes(USBF_OP_APODNET[_TRAIN], n_pix, n_el, 0) bytes.
+ *   ws      workspace of usbf_workspace_bytes(USBF_OP_APODNET_TRAIN, n_pix, n_el, 0) bytes for
+ *           the train step and the gradients; the forward pass keeps its activations in LDS and
+ *           needs none (usbf_workspace_bytes(USBF_OP_APODNET, ...) = 0, ws may be NULL).
  *   loss    device float receiving the step's loss (before the update), or NULL.
  * usbf_apodnet_gradients returns the loss gradient [10657] without updating anything.
  */

@@ -16,6 +16,8 @@
 //   A[i][k], i = l % 32, k = 8 (l / 32) + 0..7        (8 bf16 per lane)
 //   B[k][j], j = l % 32, k = 8 (l / 32) + 0..7
 //   D[i][j], j = l % 32, i = 8 (r / 4) + 4 (l / 32) + r % 4, r = 0..15  (16 floats per lane)
+#include <type_traits>
+
 #include "common.h"
 
 namespace usbf {
@@ -104,21 +106,6 @@ __global__ void pack_kernel(NetState st) {
   }
 }
 
-// ---------------------------------------------------------------- input normalisation
-
-// a0[p][m] = bf16(x[p][m] / sqrt(mean_m x^2 + 1e-12)); one wave per pixel
-__global__ void normalise_kernel(const float* __restrict__ x, int n_pix, int M, __bf16* __restrict__ a0) {
-  const int lane = threadIdx.x % 64;
-  const int p = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
-  if (p >= n_pix) return;
-  const float* xp = x + size_t(p) * M;
-  float ss = 0.0f;
-  for (int m = lane; m < M; m += 64) ss = __builtin_fmaf(xp[m], xp[m], ss);
-  for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
-  const float inv = 1.0f / sqrtf(ss / float(M) + 1e-12f);
-  for (int m = lane; m < M; m += 64) a0[size_t(p) * M + m] = __bf16(xp[m] * inv);
-}
-
 // ---------------------------------------------------------------- convolution on MFMA
 
 enum Epilogue { kRelu = 0, kLinear = 1, kMasked = 2 };
@@ -188,6 +175,119 @@ __global__ __launch_bounds__(kNetThreads) void conv_kernel(const __bf16* __restr
         }
       }
     }
+  }
+}
+
+// ---------------------------------------------------------------- fused forward
+
+// The whole forward pass of one pixel in one wave, activations kept in LDS: normalise into a0,
+// then the four convolutions, each layer's 32-position tiles read from one LDS buffer and
+// written (bias, ReLU, bf16) into the other.  The packed weights of all four layers stay in
+// registers for the wave's lifetime.  With SAVE the layer inputs a0..a3 are also written to
+// global memory for the backward pass.
+// LDS per wave: a0 [M + 16] bf16 (position m at index m + 2, zeros around), two buffers
+// [M + 4][32] bf16 (position m at row m + 2; rows 0, 1, M + 2, M + 3 stay zero).
+__host__ __device__ constexpr size_t fused_lds_bytes(int M) {
+  return (size_t(M + 16) + 2 * size_t(M + 4) * kNC) * sizeof(__bf16);
+}
+
+template <bool SAVE>
+__global__ __launch_bounds__(64) void fused_forward_kernel(const float* __restrict__ x, int n_pix, int M,
+                                                           const __bf16* __restrict__ packed,
+                                                           const float* __restrict__ params, float* __restrict__ w,
+                                                           __bf16* __restrict__ a0g, __bf16* __restrict__ a1g,
+                                                           __bf16* __restrict__ a2g, __bf16* __restrict__ a3g) {
+  extern __shared__ __align__(16) __bf16 lds[];
+  __bf16* a0 = lds;
+  __bf16* bufA = lds + (M + 16);
+  __bf16* bufB = bufA + (M + 4) * kNC;
+  const int lane = threadIdx.x;
+  const int j = lane % 32, hi = lane / 32, i = lane % 32;
+  const int n_mt = M / 32;
+
+  const bf16x8 w1 = *reinterpret_cast<const bf16x8*>(packed + kPkF1 + lane * 8);
+  bf16x8 w2[10], w3[10], w4[10];
+#pragma unroll
+  for (int s = 0; s < 10; ++s) {
+    w2[s] = *reinterpret_cast<const bf16x8*>(packed + kPkF2 + (s * 64 + lane) * 8);
+    w3[s] = *reinterpret_cast<const bf16x8*>(packed + kPkF3 + (s * 64 + lane) * 8);
+    w4[s] = *reinterpret_cast<const bf16x8*>(packed + kPkF4 + (s * 64 + lane) * 8);
+  }
+  const float b1 = params[kB1 + j], b2 = params[kB2 + j], b3 = params[kB3 + j], b4 = params[kB4];
+
+  // zero margins (never written afterwards)
+  for (int k = lane; k < 16; k += 64) a0[k < 2 ? k : M + k] = __bf16(0.0f);  // 0, 1, M + 2 .. M + 15
+  for (int k = lane; k < 4 * kNC; k += 64) {
+    const int row = k / kNC < 2 ? k / kNC : M + k / kNC;  // rows 0, 1, M + 2, M + 3
+    bufA[row * kNC + k % kNC] = __bf16(0.0f);
+    bufB[row * kNC + k % kNC] = __bf16(0.0f);
+  }
+
+  // 32 x 32 channel layer from `src` into `dst` (bias + ReLU) or, for the last layer, into w
+  auto layer32 = [&](const __bf16* src, const bf16x8* wk, auto last_, float bias, __bf16* dst, float* wout) {
+    constexpr bool LAST = decltype(last_)::value;
+    for (int mt = 0; mt < n_mt; ++mt) {
+      f32x16 acc = {};
+#pragma unroll
+      for (int s = 0; s < 10; ++s) {
+        const int t = s / 2, ci0 = (s % 2) * 16 + 8 * hi;
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(src + (32 * mt + i + t) * kNC + ci0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, wk[s], acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = 32 * mt + 8 * (r / 4) + 4 * hi + (r % 4);
+        if constexpr (LAST) {
+          if (j == 0) wout[m] = acc[r] + bias;
+        } else {
+          dst[(m + 2) * kNC + j] = __bf16(fmaxf(acc[r] + bias, 0.0f));
+        }
+      }
+    }
+  };
+  // copy the M rows of a 32-channel LDS buffer to global [M][32] with 16-byte stores
+  auto save32 = [&](const __bf16* buf, __bf16* g) {
+    for (int k = lane; k < M * 4; k += 64)
+      reinterpret_cast<uint4*>(g)[k] = reinterpret_cast<const uint4*>(buf + 2 * kNC)[k];
+  };
+
+  for (int p = blockIdx.x; p < n_pix; p += gridDim.x) {
+    __syncthreads();  // the previous pixel is done with a0 and the buffers
+    const float* xp = x + size_t(p) * M;
+    float ss = 0.0f;
+    for (int m = lane; m < M; m += 64) ss = __builtin_fmaf(xp[m], xp[m], ss);
+    for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
+    const float inv = 1.0f / sqrtf(ss / float(M) + 1e-12f);
+    for (int m = lane; m < M; m += 64) {
+      const __bf16 v = __bf16(xp[m] * inv);
+      a0[m + 2] = v;
+      if constexpr (SAVE) a0g[size_t(p) * M + m] = v;
+    }
+    __syncthreads();
+    // layer 1 (one input channel): A[i][k] = a0[32 mt + i + k - 2] for k < 5
+    for (int mt = 0; mt < n_mt; ++mt) {
+      bf16x8 a;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = 8 * hi + e;
+        a[e] = (k < kKS) ? a0[32 * mt + i + k] : __bf16(0.0f);
+      }
+      f32x16 acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, w1, f32x16{}, 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = 32 * mt + 8 * (r / 4) + 4 * hi + (r % 4);
+        bufA[(m + 2) * kNC + j] = __bf16(fmaxf(acc[r] + b1, 0.0f));
+      }
+    }
+    __syncthreads();
+    if constexpr (SAVE) save32(bufA, a1g + size_t(p) * M * kNC);
+    layer32(bufA, w2, std::false_type{}, b2, bufB, nullptr);
+    __syncthreads();
+    if constexpr (SAVE) save32(bufB, a2g + size_t(p) * M * kNC);
+    layer32(bufB, w3, std::false_type{}, b3, bufA, nullptr);
+    __syncthreads();
+    if constexpr (SAVE) save32(bufA, a3g + size_t(p) * M * kNC);
+    layer32(bufA, w4, std::true_type{}, b4, nullptr, w + size_t(p) * M);
   }
 }
 
@@ -394,6 +494,7 @@ size_t net_ws_bytes(int64_t n_pix, int64_t M, bool train) {
   const size_t act1 = align256(size_t(n_pix) * M * sizeof(__bf16));
   const size_t act32 = align256(size_t(n_pix) * M * kNC * sizeof(__bf16));
   const size_t wout = align256(size_t(n_pix) * M * sizeof(float));
+  if (!train) return 0;  // the fused forward pass needs no workspace
   size_t b = act1 + 3 * act32 + wout;
   if (train)
     b += act1 + 3 * act32 + align256(size_t(kWgradBlocks) * (kNC * kKS * kNC + kNC) * sizeof(float)) +
@@ -442,13 +543,22 @@ static void launch_wgrad(const __bf16* g, const __bf16* a, int n_pix, int M, flo
   hipLaunchKernelGGL(reduce_grad_kernel, dim3(8), dim3(256), 0, s, part, blocks, CO, NK, w_off, b_off, grad);
 }
 
-static void net_forward(const NetState& st, const float* x, int n_pix, int M, const NetWs& w, hipStream_t s) {
-  const float* P = st.params;
-  hipLaunchKernelGGL(normalise_kernel, dim3((n_pix + 3) / 4), dim3(kNetThreads), 0, s, x, n_pix, M, w.a0);
-  launch_conv<1, 32, kRelu>(w.a0, n_pix, M, st.packed + kPkF1, P + kB1, nullptr, w.a1, nullptr, s);
-  launch_conv<32, 32, kRelu>(w.a1, n_pix, M, st.packed + kPkF2, P + kB2, nullptr, w.a2, nullptr, s);
-  launch_conv<32, 32, kRelu>(w.a2, n_pix, M, st.packed + kPkF3, P + kB3, nullptr, w.a3, nullptr, s);
-  launch_conv<32, 1, kLinear>(w.a3, n_pix, M, st.packed + kPkF4, P + kB4, nullptr, nullptr, w.w, s);
+static int fused_grid(int n_pix) {
+  int dev = 0, n_cu = 256;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+  return std::max(1, std::min(n_pix, 16 * n_cu));
+}
+
+// forward pass; with `save` the layer inputs go to the workspace for the backward pass
+static void net_forward(const NetState& st, const float* x, int n_pix, int M, const NetWs& w, bool save,
+                        hipStream_t s) {
+  const size_t lds = fused_lds_bytes(M);
+  if (save)
+    hipLaunchKernelGGL(fused_forward_kernel<true>, dim3(fused_grid(n_pix)), dim3(64), lds, s, x, n_pix, M, st.packed,
+                       st.params, w.w, w.a0, w.a1, w.a2, w.a3);
+  else
+    hipLaunchKernelGGL(fused_forward_kernel<false>, dim3(fused_grid(n_pix)), dim3(64), lds, s, x, n_pix, M, st.packed,
+                       st.params, w.w, nullptr, nullptr, nullptr, nullptr);
 }
 
 static int check_net_args(int n_pix, int M) {
@@ -482,12 +592,12 @@ extern "C" int usbf_apodnet_forward(const void* state, const float* x, int32_t n
   USBF_REQUIRE(state && x && w, USBF_EINVAL, "null state, x or w");
   int st_ = check_net_args(n_pix, n_el);
   if (st_) return st_;
-  const size_t need = net_ws_bytes(n_pix, n_el, false);
-  USBF_REQUIRE(ws && ws_bytes >= need, USBF_EWORKSPACE, "apodnet forward needs %zu workspace bytes", need);
+  (void)ws;  // the fused forward pass keeps its activations in LDS
+  (void)ws_bytes;
   const NetState st = carve_state(const_cast<void*>(state));
-  NetWs wsp = carve_ws(ws, n_pix, n_el, false);
+  NetWs wsp{};
   wsp.w = w;  // the last layer writes the caller's buffer
-  net_forward(st, x, n_pix, n_el, wsp, stream);
+  net_forward(st, x, n_pix, n_el, wsp, false, stream);
   return check_launch("apodnet forward");
 }
 
@@ -502,7 +612,7 @@ extern "C" int usbf_apodnet_train_step(void* state, const float* x, const float*
   const NetState st = carve_state(state);
   NetWs w = carve_ws(ws, n_pix, n_el, true);
   const int M = n_el;
-  net_forward(st, x, n_pix, M, w, stream);
+  net_forward(st, x, n_pix, M, w, true, stream);
   const int lb = std::min(kLossBlocks, (n_pix * M + 255) / 256);
   hipLaunchKernelGGL(loss_kernel, dim3(lb), dim3(kNetThreads), 0, stream, w.w, w_target, n_pix, M, w.g4, w.loss_part);
   if (loss)
@@ -532,7 +642,7 @@ extern "C" int usbf_apodnet_gradients(const void* state, const float* x, const f
   const NetState st = carve_state(const_cast<void*>(state));
   NetWs w = carve_ws(ws, n_pix, n_el, true);
   const int M = n_el;
-  net_forward(st, x, n_pix, M, w, stream);
+  net_forward(st, x, n_pix, M, w, true, stream);
   const int lb = std::min(kLossBlocks, (n_pix * M + 255) / 256);
   hipLaunchKernelGGL(loss_kernel, dim3(lb), dim3(kNetThreads), 0, stream, w.w, w_target, n_pix, M, w.g4, w.loss_part);
   launch_wgrad<32, 1>(w.g4, w.a3, n_pix, M, w.part, grad, kW4, kB4, stream);

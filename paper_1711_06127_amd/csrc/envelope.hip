@@ -161,9 +161,26 @@ __global__ __launch_bounds__(kEnvThreads) void envelope_kernel(const float* in, 
   const bool even = (n % 2) == 0;
   const float inv_n = 1.0f / float(n);
   __shared__ float red[kEnvThreads / 64];
-  for (int64_t row = blockIdx.x; row < n_rows; row += gridDim.x) {
+  // rows are taken grid-stride; the next row is loaded into registers while this one is
+  // transformed, so its memory latency hides behind the FFTs
+  constexpr int kPer = kMaxEnvelopeLength / kEnvThreads;
+  float pre[kPer];
+  auto load_row = [&](int64_t row) {
     const float* x = in + row * n;
-    for (int k = threadIdx.x; k < n; k += kEnvThreads) buf[0][k] = {x[k], 0.0f};
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int k = threadIdx.x + i * kEnvThreads;
+      pre[i] = (k < n) ? x[k] : 0.0f;
+    }
+  };
+  if (int64_t(blockIdx.x) < n_rows) load_row(blockIdx.x);
+  for (int64_t row = blockIdx.x; row < n_rows; row += gridDim.x) {
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int k = threadIdx.x + i * kEnvThreads;
+      if (k < n) buf[0][k] = {pre[i], 0.0f};
+    }
+    if (row + gridDim.x < n_rows) load_row(row + gridDim.x);
     __syncthreads();
     int cur = fft_lds(buf[0], buf[1], tw, P);
     // analytic-signal weights, then conjugate for the inverse-by-forward transform
@@ -226,7 +243,12 @@ bool envelope_length_ok(int n) {
 int envelope_enqueue(const float* in, int64_t n_rows, int n, float* env, float* row_max, hipStream_t s) {
   FftPlan P;
   USBF_REQUIRE(make_fft_plan(n, &P) == USBF_OK, USBF_EUNSUPPORTED, "envelope length %d has a prime factor above 31", n);
-  const int64_t blocks = std::min<int64_t>(n_rows, 8192);
+  // a resident grid (the twiddle table is built once per workgroup): 160 KB of LDS per CU
+  // holds 160 KB / (24 n) workgroups
+  int dev = 0, n_cu = 256;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+  const int per_cu = std::max(1, std::min(8, int(163840 / (size_t(3) * n * sizeof(c32) + 64))));
+  const int64_t blocks = std::min<int64_t>(n_rows, int64_t(n_cu) * per_cu);
   const size_t lds = size_t(3) * n * sizeof(c32);
   hipLaunchKernelGGL(envelope_kernel, dim3(unsigned(blocks)), dim3(kEnvThreads), lds, s, in, n_rows, P, env,
                      row_max);
