@@ -152,7 +152,7 @@ int make_plan(const usbf_batch_item* items, int n, int groups_per_cu, int cost_o
     dev[i].out = it.lines;
   }
   const size_t lds = persistent_lds_bytes(max_el[0], max_el[1]);
-  USBF_REQUIRE(lds <= 65536, USBF_EUNSUPPORTED, "items with %d / %d elements (1- / 4-line tiles) exceed the tile LDS",
+  USBF_REQUIRE(lds <= 160 * 1024, USBF_EUNSUPPORTED, "items with %d / %d elements (1- / 4-line tiles) exceed the tile LDS",
                max_el[0], max_el[1]);
   // unit order: most expensive units (most elements) first, stable
   std::vector<int> order(n);

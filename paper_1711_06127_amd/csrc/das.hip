@@ -25,9 +25,32 @@
 namespace usbf {
 
 constexpr int kDasThreads = 256;
-constexpr int kMaxChunk = 8;
-constexpr int kWindowMargin = 32;     // samples beyond 2 * depths per line in a window
-constexpr int kBufferBytes = 24576;   // one staging buffer (two per workgroup)
+// Tile tunables (compile-time; the defaults are the fastest measured on gfx950): the bytes of
+// one staging buffer (two per workgroup) for multi-line tiles, single-line multi-frame tiles
+// and single-frame tiles, and the most elements per chunk.
+#ifndef USBF_DAS_BUF_MULTI
+#define USBF_DAS_BUF_MULTI 16384
+#endif
+#ifndef USBF_DAS_BUF_SINGLE
+#define USBF_DAS_BUF_SINGLE 78336
+#endif
+#ifndef USBF_DAS_BUF_FRAME
+#define USBF_DAS_BUF_FRAME 24576
+#endif
+#ifndef USBF_DAS_MAX_CHUNK
+#define USBF_DAS_MAX_CHUNK 12
+#endif
+constexpr int kMaxChunk = USBF_DAS_MAX_CHUNK;
+#ifndef USBF_DAS_WINDOW_MARGIN
+#define USBF_DAS_WINDOW_MARGIN 32
+#endif
+constexpr int kWindowMargin = USBF_DAS_WINDOW_MARGIN;  // samples beyond 2 * depths per line in a window
+constexpr int kMaxTileLds = 160 * 1024;  // LDS a workgroup may use on gfx950
+
+__host__ __device__ constexpr int buffer_bytes(int G, int FS) {
+  return G > 1 ? USBF_DAS_BUF_MULTI : (FS > 1 ? USBF_DAS_BUF_SINGLE : USBF_DAS_BUF_FRAME);
+}
+__host__ __device__ constexpr int max_chunk(int FS) { return FS > 1 ? kMaxChunk : (kMaxChunk < 8 ? kMaxChunk : 8); }
 
 template <int FS>
 struct FVec;
@@ -51,15 +74,16 @@ struct FVec<4> {
 };
 
 // Compile-time shape of a tile: G lines x TD depths; a window of SPAN samples per element for
-// depth_step <= 2; EC elements per chunk so that one staging buffer fits kBufferBytes; IPT
+// depth_step <= 2; EC elements per chunk so that one staging buffer fits buffer_bytes(G, FS); IPT
 // staging items (4 samples x FS frames) per lane.
 template <int G, int FS>
 struct Shape {
   static constexpr int TD = kDasThreads / G;
   static constexpr int SPAN = 2 * TD + kWindowMargin;
-  static constexpr int EC0 = kBufferBytes / (SPAN * FS * 4);
-  static constexpr int EC = EC0 < kMaxChunk ? (EC0 < 1 ? 1 : EC0) : kMaxChunk;
+  static constexpr int EC0 = buffer_bytes(G, FS) / (SPAN * FS * 4);
+  static constexpr int EC = EC0 < max_chunk(FS) ? (EC0 < 1 ? 1 : EC0) : max_chunk(FS);
   static constexpr int BUFV = EC * SPAN;  // staging buffer length in frame vectors
+  static constexpr int BSTRIDE = BUFV + 1; // buffer pitch: each buffer ends in a zero vector
   static constexpr int IPT = (EC * (SPAN / 4) + kDasThreads - 1) / kDasThreads;
 };
 
@@ -70,18 +94,19 @@ struct Shape {
 // depths read taps depth_step = 2 samples apart, so their reads are consecutive in LDS.
 template <int G, int FS>
 struct TileLds {
-  typename FVec<FS>::T* win;  // [2][BUFV]
+  typename FVec<FS>::T* win;  // [2][BUFV + 1]: window data, then one all-zero frame vector
   float4* geo;                // [G][n_el]: (A, B, dx, dy)
   LineGeom* lines;            // [G]
   int2* wnd;                  // [n_el]: (lo, hi)
   int* flg;                   // [n_el]: bit 0 needed, bit 1 staged
 };
 
-// two staging buffers plus one all-zero frame vector (kept zero for the whole kernel): taps
-// that contribute nothing read it, so the accumulation needs no branch
+// two staging buffers, each followed by an all-zero frame vector (kept zero for the whole
+// kernel): taps that contribute nothing read it, at the same offset in either buffer, so the
+// accumulation needs neither a branch nor a per-buffer select
 template <int G, int FS>
 __host__ __device__ constexpr size_t window_bytes() {
-  return (2 * size_t(Shape<G, FS>::BUFV) + 1) * FS * sizeof(float);
+  return 2 * size_t(Shape<G, FS>::BSTRIDE) * FS * sizeof(float);
 }
 
 template <int G, int FS>
@@ -262,13 +287,14 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
   const int t_grp = (t0 >= 0 && t0 < a.n_tx) ? t0 : -1;
 
   // ---- prologue: line constants, per-(line, element) receive constants, tap windows
-  constexpr int ZERO = 2 * SH::BUFV;
+  constexpr int ZERO = SH::BUFV;  // index of a buffer's zero vector
   if (tid < G) line_geom(a, min(l0 + tid, a.n_lines - 1), t.lines[tid]);
   if (tid == 0) {
     V z;
 #pragma unroll
     for (int f = 0; f < FS; ++f) FVec<FS>::set(z, f, 0.0f);
     t.win[ZERO] = z;
+    t.win[SH::BSTRIDE + ZERO] = z;
   }
   for (int e = tid; e < a.n_el; e += kDasThreads) {
     t.wnd[e] = make_int2(INT_MAX, INT_MIN);
@@ -366,7 +392,7 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
     const int e0 = c * ta.ec;
 #pragma unroll
     for (int k = 0; k < SH::EC; ++k) {
-      T.off0[k] = T.off1[k] = ZERO;
+      T.off0[k] = T.off1[k] = ZERO * int(sizeof(V));
       T.w0[k] = T.w1[k] = 0.0f;
       if (k >= ta.ec) continue;
       const int e = min(e0 + k, a.n_el - 1);
@@ -387,8 +413,9 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
       const int wbase = k * ta.span;
       const int p0 = ta.pshift ? ((rel & 1) * half + (rel >> 1)) : rel;
       const int p1 = ta.pshift ? (((rel + 1) & 1) * half + ((rel + 1) >> 1)) : rel + 1;
-      T.off0[k] = (ok && in_win) ? wbase + p0 : ZERO;
-      T.off1[k] = (ok && in_win) ? wbase + p1 : ZERO;
+      // byte offsets within a buffer
+      T.off0[k] = ((ok && in_win) ? wbase + p0 : ZERO) * int(sizeof(V));
+      T.off1[k] = ((ok && in_win) ? wbase + p1 : ZERO) * int(sizeof(V));
       T.slow |= (ok && !in_win) ? (1u << k) : 0u;
     }
     return T;
@@ -428,14 +455,12 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
     // sum one stage (frames s FS .. s FS + FS - 1 of the block) from LDS buffer `buf`
     auto sum_stage = [&](const Taps& T, int buf, auto s_) {
       constexpr int s = decltype(s_)::value;
-      const V* w = t.win + buf * SH::BUFV;
+      const char* w = reinterpret_cast<const char*>(t.win + buf * SH::BSTRIDE);
 #pragma unroll
       for (int k = 0; k < SH::EC; ++k) {
         // the zero vector sits after both buffers: index relative to this buffer
-        const int i0 = T.off0[k] == ZERO ? ZERO - buf * SH::BUFV : T.off0[k];
-        const int i1 = T.off1[k] == ZERO ? ZERO - buf * SH::BUFV : T.off1[k];
-        const V x0 = w[i0];
-        const V x1 = w[i1];
+        const V x0 = *reinterpret_cast<const V*>(w + T.off0[k]);
+        const V x1 = *reinterpret_cast<const V*>(w + T.off1[k]);
 #pragma unroll
         for (int f = 0; f < FS; ++f)
           acc[s * FS + f] = __builtin_fmaf(T.w0[k], FVec<FS>::get(x0, f),
@@ -468,7 +493,7 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
         sum_stage(T, P, std::integral_constant<int, 0>{});
         __builtin_amdgcn_sched_barrier(0);
         if (cn < n_chunks && stage_any)
-          store_stage<VEC, G, FS, IPT>(pf[P ^ 1], items_n, t.win + (P ^ 1) * SH::BUFV, ta.span, ta.pshift);
+          store_stage<VEC, G, FS, IPT>(pf[P ^ 1], items_n, t.win + (P ^ 1) * SH::BSTRIDE, ta.span, ta.pshift);
         __syncthreads();
         if (T.slow) slow_taps(T, c, fb, acc);
         c = cn;
@@ -504,7 +529,7 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
           const bool has_next = last ? (cn < n_chunks && stage_any) : stage_any;
           if (has_next)
             store_stage<VEC, G, FS, IPT>(pf[(s + 1) & 1], last ? next_items : items,
-                                         t.win + ((s + 1) & 1) * SH::BUFV, ta.span, ta.pshift);
+                                         t.win + ((s + 1) & 1) * SH::BSTRIDE, ta.span, ta.pshift);
           __syncthreads();
         };
         static_for<NS>(step);
@@ -599,6 +624,13 @@ __global__ void delay_index_kernel(DasArgs a, int32_t* __restrict__ i0, uint8_t*
   }
 }
 
+// dynamic LDS above 64 KB has to be allowed per kernel
+static int allow_lds(const void* kernel, size_t lds) {
+  const hipError_t e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+  if (e != hipSuccess) return fail(USBF_EDEVICE, "cannot allow %zu bytes of LDS: %s", lds, hipGetErrorString(e));
+  return USBF_OK;
+}
+
 template <int G, int FB, int FS>
 static int launch_das(const int16_t* rf, int frame0, int n_blocks, const DasArgs& a, float* out, hipStream_t s) {
   using SH = Shape<G, FS>;
@@ -614,14 +646,18 @@ static int launch_das(const int16_t* rf, int frame0, int n_blocks, const DasArgs
   const int64_t blocks = int64_t((a.n_lines + G - 1) / G) * ta.n_dtiles;
   if (blocks > 0x7fffffff) return fail(USBF_EUNSUPPORTED, "too many tiles");
   const size_t lds = tile_lds_bytes<G, FS>(a.n_el);
-  if (lds > 65536) return fail(USBF_EUNSUPPORTED, "%d elements need %zu bytes of LDS per tile", a.n_el, lds);
+  if (lds > size_t(kMaxTileLds))
+    return fail(USBF_EUNSUPPORTED, "%d elements need %zu bytes of LDS per tile", a.n_el, lds);
   const bool vec = (a.n_samples % 4) == 0 && (reinterpret_cast<uintptr_t>(rf) & 7) == 0;
-  if (vec)
+  if (vec) {
+    if (lds > 65536 && allow_lds((const void*)das_tile_kernel<true, G, FB, FS>, lds)) return USBF_EDEVICE;
     hipLaunchKernelGGL((das_tile_kernel<true, G, FB, FS>), dim3(unsigned(blocks)), dim3(kDasThreads), lds, s, rf,
                        frame0, n_blocks, a, ta, out);
-  else
+  } else {
+    if (lds > 65536 && allow_lds((const void*)das_tile_kernel<false, G, FB, FS>, lds)) return USBF_EDEVICE;
     hipLaunchKernelGGL((das_tile_kernel<false, G, FB, FS>), dim3(unsigned(blocks)), dim3(kDasThreads), lds, s, rf,
                        frame0, n_blocks, a, ta, out);
+  }
   return check_launch("das_tile_kernel");
 }
 
@@ -685,6 +721,9 @@ size_t persistent_lds_bytes(int max_n_el_g1, int max_n_el_g4) {
 int launch_persistent(const BatchItemDev* d_items, int n_items, int total_units, int* counter, bool vec, int grid,
                       size_t lds, hipStream_t s) {
   hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, counter);
+  if (lds > 65536 && allow_lds(vec ? (const void*)das_persistent_kernel<true> : (const void*)das_persistent_kernel<false>,
+                               lds))
+    return USBF_EDEVICE;
   if (vec)
     hipLaunchKernelGGL(das_persistent_kernel<true>, dim3(grid), dim3(kDasThreads), lds, s, d_items, n_items,
                        total_units, counter);

@@ -3,8 +3,8 @@
 // positive and removing the negative frequencies.
 //
 // One workgroup owns a row at a time (grid-stride over rows so the twiddle table is built
-// once per workgroup) and runs a mixed-radix self-sorting Stockham FFT in LDS: radix 2, 3, 4,
-// 5 butterflies, and the plain DFT for prime factors 7 ... 31.
+// once per workgroup) and runs a mixed-radix self-sorting Stockham FFT in LDS: radix 8, 4, 2,
+// 3, 5 butterflies, and the plain DFT for prime factors 7 ... 31.
 // The inverse transform is done as a forward transform of the conjugate: the magnitude of
 // conj(FFT(conj(X))) / n needs no final conjugation.
 #include "common.h"
@@ -49,6 +49,25 @@ __device__ inline void dft4(c32* v) {
   v[1] = cadd(t1, t3);
   v[3] = csub(t1, t3);
 }
+// size 8: two size-4 transforms of the even and odd inputs, combined with e^{-2 pi i k / 8}
+__device__ inline void dft8(c32* v) {
+  const float h = 0.70710678118654752440f;  // sqrt(1/2)
+  c32 a[4] = {v[0], v[2], v[4], v[6]}, b[4] = {v[1], v[3], v[5], v[7]};
+  dft4(a);
+  dft4(b);
+  const c32 t1 = {h * (b[1].x + b[1].y), h * (b[1].y - b[1].x)};    // b1 e^{-i pi/4}
+  const c32 t2 = mul_mi(b[2]);                                       // b2 e^{-i pi/2}
+  const c32 t3 = {h * (b[3].y - b[3].x), -h * (b[3].x + b[3].y)};   // b3 e^{-3 i pi/4}
+  v[0] = cadd(a[0], b[0]);
+  v[4] = csub(a[0], b[0]);
+  v[1] = cadd(a[1], t1);
+  v[5] = csub(a[1], t1);
+  v[2] = cadd(a[2], t2);
+  v[6] = csub(a[2], t2);
+  v[3] = cadd(a[3], t3);
+  v[7] = csub(a[3], t3);
+}
+
 __device__ inline void dft3(c32* v) {
   const float h = 0.86602540378443864676f;  // sqrt(3)/2
   c32 s = cadd(v[1], v[2]);
@@ -76,20 +95,18 @@ __device__ inline void dft5(c32* v) {
   v[3] = csub(p2, q2);
 }
 
-// Forward DFT of prime size R by its definition, y_k = sum_m v_m e^{-2 pi i m k / R}; the
-// roots come from the n-point table (tw[q * n / R] = e^{-2 pi i q / R}).
+// Forward DFT of prime size R by its definition, y_k = sum_m v_m e^{-2 pi i m k / R}, each
+// output written straight to its destination; the roots come from the n-point table
+// (tw[q * n / R] = e^{-2 pi i q / R}).
 template <int R>
-__device__ inline void dft_prime(c32* v, const c32* __restrict__ tw, int tw_r) {
-  c32 out[R];
-#pragma unroll
+__device__ inline void dft_prime_store(const c32* v, const c32* __restrict__ tw, int tw_r, c32* __restrict__ dst,
+                                       int stride) {
   for (int k = 0; k < R; ++k) {
     c32 acc = v[0];
 #pragma unroll
     for (int m = 1; m < R; ++m) acc = cadd(acc, cmul(v[m], tw[((m * k) % R) * tw_r]));
-    out[k] = acc;
+    dst[k * stride] = acc;
   }
-#pragma unroll
-  for (int k = 0; k < R; ++k) v[k] = out[k];
 }
 
 template <int R>
@@ -106,15 +123,25 @@ __device__ inline void stage(const c32* __restrict__ a, c32* __restrict__ b, con
     if constexpr (R == 2) dft2(v);
     if constexpr (R == 3) dft3(v);
     if constexpr (R == 4) dft4(v);
-    if constexpr (R == 5) dft5(v);
-    if constexpr (R > 5) dft_prime<R>(v, tw, m);
     const int o = (j / ns) * ns * R + k;
+    if constexpr (R == 8) {
+      dft8(v);
 #pragma unroll
-    for (int r = 0; r < R; ++r) b[o + r * ns] = v[r];
+      for (int r = 0; r < R; ++r) b[o + r * ns] = v[r];
+    } else if constexpr (R > 5) {
+      dft_prime_store<R>(v, tw, m, b + o, ns);
+    } else {
+      if constexpr (R == 5) dft5(v);
+#pragma unroll
+      for (int r = 0; r < R; ++r) b[o + r * ns] = v[r];
+    }
   }
 }
 
 // Forward FFT of buf[0] (result in buf[0] or buf[1]); returns the buffer holding the result.
+// PRIMES: the plan may hold radices 7 ... 31 (kept out of the common kernel: their register
+// footprint would cut its occupancy).
+template <bool PRIMES>
 __device__ inline int fft_lds(c32* buf0, c32* buf1, const c32* tw, const FftPlan& P) {
   c32* a = buf0;
   c32* b = buf1;
@@ -123,18 +150,25 @@ __device__ inline int fft_lds(c32* buf0, c32* buf1, const c32* tw, const FftPlan
   for (int s = 0; s < P.n_stages; ++s) {
     const int R = P.radix[s];
     switch (R) {
+      case 8: stage<8>(a, b, tw, P.n, ns); break;
       case 4: stage<4>(a, b, tw, P.n, ns); break;
       case 2: stage<2>(a, b, tw, P.n, ns); break;
       case 3: stage<3>(a, b, tw, P.n, ns); break;
       case 5: stage<5>(a, b, tw, P.n, ns); break;
-      case 7: stage<7>(a, b, tw, P.n, ns); break;
-      case 11: stage<11>(a, b, tw, P.n, ns); break;
-      case 13: stage<13>(a, b, tw, P.n, ns); break;
-      case 17: stage<17>(a, b, tw, P.n, ns); break;
-      case 19: stage<19>(a, b, tw, P.n, ns); break;
-      case 23: stage<23>(a, b, tw, P.n, ns); break;
-      case 29: stage<29>(a, b, tw, P.n, ns); break;
-      default: stage<31>(a, b, tw, P.n, ns); break;
+      default:
+        if constexpr (PRIMES) {
+          switch (R) {
+            case 7: stage<7>(a, b, tw, P.n, ns); break;
+            case 11: stage<11>(a, b, tw, P.n, ns); break;
+            case 13: stage<13>(a, b, tw, P.n, ns); break;
+            case 17: stage<17>(a, b, tw, P.n, ns); break;
+            case 19: stage<19>(a, b, tw, P.n, ns); break;
+            case 23: stage<23>(a, b, tw, P.n, ns); break;
+            case 29: stage<29>(a, b, tw, P.n, ns); break;
+            default: stage<31>(a, b, tw, P.n, ns); break;
+          }
+        }
+        break;
     }
     __syncthreads();
     c32* t = a;
@@ -146,6 +180,7 @@ __device__ inline int fft_lds(c32* buf0, c32* buf1, const c32* tw, const FftPlan
   return cur;
 }
 
+template <bool PRIMES>
 __global__ __launch_bounds__(kEnvThreads) void envelope_kernel(const float* in, int64_t n_rows, FftPlan P,
                                                                float* env, float* __restrict__ row_max) {
   extern __shared__ c32 lds[];
@@ -182,7 +217,7 @@ __global__ __launch_bounds__(kEnvThreads) void envelope_kernel(const float* in, 
     }
     if (row + gridDim.x < n_rows) load_row(row + gridDim.x);
     __syncthreads();
-    int cur = fft_lds(buf[0], buf[1], tw, P);
+    int cur = fft_lds<PRIMES>(buf[0], buf[1], tw, P);
     // analytic-signal weights, then conjugate for the inverse-by-forward transform
     c32* X = buf[cur];
     for (int k = threadIdx.x; k < n; k += kEnvThreads) {
@@ -197,7 +232,7 @@ __global__ __launch_bounds__(kEnvThreads) void envelope_kernel(const float* in, 
       X[k] = {v.x * hk, -v.y * hk};
     }
     __syncthreads();
-    int cur2 = fft_lds(X, buf[cur ^ 1], tw, P);
+    int cur2 = fft_lds<PRIMES>(X, buf[cur ^ 1], tw, P);
     c32* Y = (cur2 == 0) ? X : buf[cur ^ 1];
     float mx = 0.0f;
     float* e = env + row * n;
@@ -224,7 +259,7 @@ int make_fft_plan(int n, FftPlan* P) {
   P->n = n;
   P->n_stages = 0;
   int m = n;
-  const int order[12] = {4, 2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31};
+  const int order[13] = {8, 4, 2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31};
   for (int R : order) {
     while (m % R == 0) {
       if (P->n_stages >= kMaxStages) return USBF_EUNSUPPORTED;
@@ -250,8 +285,14 @@ int envelope_enqueue(const float* in, int64_t n_rows, int n, float* env, float* 
   const int per_cu = std::max(1, std::min(8, int(163840 / (size_t(3) * n * sizeof(c32) + 64))));
   const int64_t blocks = std::min<int64_t>(n_rows, int64_t(n_cu) * per_cu);
   const size_t lds = size_t(3) * n * sizeof(c32);
-  hipLaunchKernelGGL(envelope_kernel, dim3(unsigned(blocks)), dim3(kEnvThreads), lds, s, in, n_rows, P, env,
-                     row_max);
+  bool primes = false;
+  for (int k = 0; k < P.n_stages; ++k) primes = primes || (P.radix[k] > 5 && P.radix[k] != 8);
+  if (primes)
+    hipLaunchKernelGGL(envelope_kernel<true>, dim3(unsigned(blocks)), dim3(kEnvThreads), lds, s, in, n_rows, P, env,
+                       row_max);
+  else
+    hipLaunchKernelGGL(envelope_kernel<false>, dim3(unsigned(blocks)), dim3(kEnvThreads), lds, s, in, n_rows, P, env,
+                       row_max);
   return check_launch("envelope_kernel");
 }
 
