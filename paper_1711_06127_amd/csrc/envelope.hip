@@ -27,6 +27,11 @@ struct c32 {
   float x, y;
 };
 
+// LDS arrays are padded by one element per 16 so that the strided accesses of the early
+// stages (and of the twiddle table) spread over the banks
+__host__ __device__ constexpr int pad(int i) { return i + (i >> 4); }
+__host__ __device__ constexpr int padded_len(int n) { return pad(n) + 1; }
+
 __device__ inline c32 cadd(c32 a, c32 b) { return {a.x + b.x, a.y + b.y}; }
 __device__ inline c32 csub(c32 a, c32 b) { return {a.x - b.x, a.y - b.y}; }
 __device__ inline c32 cmul(c32 a, c32 b) {
@@ -100,12 +105,12 @@ __device__ inline void dft5(c32* v) {
 // (tw[q * n / R] = e^{-2 pi i q / R}).
 template <int R>
 __device__ inline void dft_prime_store(const c32* v, const c32* __restrict__ tw, int tw_r, c32* __restrict__ dst,
-                                       int stride) {
+                                       int o, int stride) {
   for (int k = 0; k < R; ++k) {
     c32 acc = v[0];
 #pragma unroll
-    for (int m = 1; m < R; ++m) acc = cadd(acc, cmul(v[m], tw[((m * k) % R) * tw_r]));
-    dst[k * stride] = acc;
+    for (int m = 1; m < R; ++m) acc = cadd(acc, cmul(v[m], tw[pad(((m * k) % R) * tw_r)]));
+    dst[pad(o + k * stride)] = acc;
   }
 }
 
@@ -116,10 +121,10 @@ __device__ inline void stage(const c32* __restrict__ a, c32* __restrict__ b, con
   for (int j = threadIdx.x; j < m; j += kEnvThreads) {
     c32 v[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = a[j + r * m];
+    for (int r = 0; r < R; ++r) v[r] = a[pad(j + r * m)];
     const int k = j % ns;
 #pragma unroll
-    for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[r * k * tw_step]);
+    for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[pad(r * k * tw_step)]);
     if constexpr (R == 2) dft2(v);
     if constexpr (R == 3) dft3(v);
     if constexpr (R == 4) dft4(v);
@@ -127,14 +132,51 @@ __device__ inline void stage(const c32* __restrict__ a, c32* __restrict__ b, con
     if constexpr (R == 8) {
       dft8(v);
 #pragma unroll
-      for (int r = 0; r < R; ++r) b[o + r * ns] = v[r];
+      for (int r = 0; r < R; ++r) b[pad(o + r * ns)] = v[r];
     } else if constexpr (R > 5) {
-      dft_prime_store<R>(v, tw, m, b + o, ns);
+      dft_prime_store<R>(v, tw, m, b, o, ns);
     } else {
       if constexpr (R == 5) dft5(v);
 #pragma unroll
-      for (int r = 0; r < R; ++r) b[o + r * ns] = v[r];
+      for (int r = 0; r < R; ++r) b[pad(o + r * ns)] = v[r];
     }
+  }
+}
+
+// Power-of-two lengths: the same Stockham stages with every size, stride and twiddle step a
+// compile-time constant (radix 8 stages, then one radix 4 or 2 stage), so the index
+// arithmetic reduces to shifts and masks and the first stage skips its unit twiddles.
+template <int N, int R, int NS>
+__device__ inline void stage_c(const c32* __restrict__ a, c32* __restrict__ b, const c32* __restrict__ tw) {
+  constexpr int M = N / R, TWS = N / (NS * R);
+  for (int j = threadIdx.x; j < M; j += kEnvThreads) {
+    c32 v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = a[pad(j + r * M)];
+    const int k = j % NS;
+    if constexpr (NS > 1) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[pad(r * k * TWS)]);
+    }
+    if constexpr (R == 2) dft2(v);
+    if constexpr (R == 4) dft4(v);
+    if constexpr (R == 8) dft8(v);
+    const int o = (j / NS) * NS * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) b[pad(o + r * NS)] = v[r];
+  }
+}
+
+template <int N, int NS>
+__device__ inline int fft_pow2_from(c32* a, c32* b, const c32* tw, int cur) {
+  if constexpr (NS >= N) {
+    return cur;
+  } else {
+    constexpr int left = N / NS;
+    constexpr int R = left >= 8 ? 8 : left;  // radix 8 while it divides, then 4 or 2
+    stage_c<N, R, NS>(a, b, tw);
+    __syncthreads();
+    return fft_pow2_from<N, NS * R>(b, a, tw, cur ^ 1);
   }
 }
 
@@ -180,17 +222,20 @@ __device__ inline int fft_lds(c32* buf0, c32* buf1, const c32* tw, const FftPlan
   return cur;
 }
 
-template <bool PRIMES>
+// N > 0: power-of-two length N with the compile-time transform; N = 0: any supported length
+// with the plan's mixed-radix transform (PRIMES: radices above 8 present)
+template <int N, bool PRIMES>
 __global__ __launch_bounds__(kEnvThreads) void envelope_kernel(const float* in, int64_t n_rows, FftPlan P,
                                                                float* env, float* __restrict__ row_max) {
   extern __shared__ c32 lds[];
   const int n = P.n;
-  c32* buf[2] = {lds, lds + n};
-  c32* tw = lds + 2 * n;
+  const int np = padded_len(n);
+  c32* buf[2] = {lds, lds + np};
+  c32* tw = lds + 2 * np;
   for (int k = threadIdx.x; k < n; k += kEnvThreads) {
     float s, c;
     sincospif(2.0f * float(k) / float(n), &s, &c);
-    tw[k] = {c, -s};
+    tw[pad(k)] = {c, -s};
   }
   const int half = n / 2;
   const bool even = (n % 2) == 0;
@@ -213,11 +258,15 @@ __global__ __launch_bounds__(kEnvThreads) void envelope_kernel(const float* in, 
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
       const int k = threadIdx.x + i * kEnvThreads;
-      if (k < n) buf[0][k] = {pre[i], 0.0f};
+      if (k < n) buf[0][pad(k)] = {pre[i], 0.0f};
     }
     if (row + gridDim.x < n_rows) load_row(row + gridDim.x);
     __syncthreads();
-    int cur = fft_lds<PRIMES>(buf[0], buf[1], tw, P);
+    int cur;
+    if constexpr (N > 0)
+      cur = fft_pow2_from<N, 1>(buf[0], buf[1], tw, 0);
+    else
+      cur = fft_lds<PRIMES>(buf[0], buf[1], tw, P);
     // analytic-signal weights, then conjugate for the inverse-by-forward transform
     c32* X = buf[cur];
     for (int k = threadIdx.x; k < n; k += kEnvThreads) {
@@ -228,16 +277,20 @@ __global__ __launch_bounds__(kEnvThreads) void envelope_kernel(const float* in, 
         hk = 2.0f;
       else
         hk = 0.0f;
-      c32 v = X[k];
-      X[k] = {v.x * hk, -v.y * hk};
+      c32 v = X[pad(k)];
+      X[pad(k)] = {v.x * hk, -v.y * hk};
     }
     __syncthreads();
-    int cur2 = fft_lds<PRIMES>(X, buf[cur ^ 1], tw, P);
+    int cur2;
+    if constexpr (N > 0)
+      cur2 = fft_pow2_from<N, 1>(X, buf[cur ^ 1], tw, 0);
+    else
+      cur2 = fft_lds<PRIMES>(X, buf[cur ^ 1], tw, P);
     c32* Y = (cur2 == 0) ? X : buf[cur ^ 1];
     float mx = 0.0f;
     float* e = env + row * n;
     for (int k = threadIdx.x; k < n; k += kEnvThreads) {
-      c32 v = Y[k];
+      c32 v = Y[pad(k)];
       float m = sqrtf(__builtin_fmaf(v.x, v.x, v.y * v.y)) * inv_n;
       e[k] = m;
       mx = fmaxf(mx, m);
@@ -282,17 +335,23 @@ int envelope_enqueue(const float* in, int64_t n_rows, int n, float* env, float* 
   // holds 160 KB / (24 n) workgroups
   int dev = 0, n_cu = 256;
   if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
-  const int per_cu = std::max(1, std::min(8, int(163840 / (size_t(3) * n * sizeof(c32) + 64))));
+  const size_t lds = size_t(3) * padded_len(n) * sizeof(c32);
+  const int per_cu = std::max(1, std::min(8, int(163840 / (lds + 64))));
   const int64_t blocks = std::min<int64_t>(n_rows, int64_t(n_cu) * per_cu);
-  const size_t lds = size_t(3) * n * sizeof(c32);
   bool primes = false;
   for (int k = 0; k < P.n_stages; ++k) primes = primes || (P.radix[k] > 5 && P.radix[k] != 8);
-  if (primes)
-    hipLaunchKernelGGL(envelope_kernel<true>, dim3(unsigned(blocks)), dim3(kEnvThreads), lds, s, in, n_rows, P, env,
-                       row_max);
-  else
-    hipLaunchKernelGGL(envelope_kernel<false>, dim3(unsigned(blocks)), dim3(kEnvThreads), lds, s, in, n_rows, P, env,
-                       row_max);
+  const dim3 grid = dim3(static_cast<unsigned>(blocks)), block = dim3(kEnvThreads);
+  switch (n) {
+    case 2048: hipLaunchKernelGGL((envelope_kernel<2048, false>), grid, block, lds, s, in, n_rows, P, env, row_max); break;
+    case 1024: hipLaunchKernelGGL((envelope_kernel<1024, false>), grid, block, lds, s, in, n_rows, P, env, row_max); break;
+    case 512: hipLaunchKernelGGL((envelope_kernel<512, false>), grid, block, lds, s, in, n_rows, P, env, row_max); break;
+    case 256: hipLaunchKernelGGL((envelope_kernel<256, false>), grid, block, lds, s, in, n_rows, P, env, row_max); break;
+    default:
+      if (primes)
+        hipLaunchKernelGGL((envelope_kernel<0, true>), grid, block, lds, s, in, n_rows, P, env, row_max);
+      else
+        hipLaunchKernelGGL((envelope_kernel<0, false>), grid, block, lds, s, in, n_rows, P, env, row_max);
+  }
   return check_launch("envelope_kernel");
 }
 
