@@ -35,7 +35,7 @@ constexpr int kDasThreads = 256;
 #define USBF_DAS_BUF_SINGLE 78336
 #endif
 #ifndef USBF_DAS_BUF_FRAME
-#define USBF_DAS_BUF_FRAME 24576
+#define USBF_DAS_BUF_FRAME 6528
 #endif
 #ifndef USBF_DAS_MAX_CHUNK
 #define USBF_DAS_MAX_CHUNK 12
@@ -89,16 +89,19 @@ struct Shape {
 
 // LDS of one workgroup: two staging buffers, the per-(line, element) receive constants of the
 // G lines, their LineGeom, and per element the tap window [lo, hi] and flags.
-// A staged window holds the samples of one element for FS frames; with pshift = 1 it is split
+// A staged window holds the samples of one element for FS frames; with pshift = 1 (and FS > 1:
+// single-frame windows are read 4 bytes per lane, where the split does not pay) it is split
 // into even and odd samples (sample i at index (i & 1) * span/2 + i/2): lanes on consecutive
 // depths read taps depth_step = 2 samples apart, so their reads are consecutive in LDS.
 template <int G, int FS>
 struct TileLds {
   typename FVec<FS>::T* win;  // [2][BUFV + 1]: window data, then one all-zero frame vector
-  float4* geo;                // [G][n_el]: (A, B, dx, dy)
+  float2* geo;                // [G][n_el]: (A, B) of the receive path
+  float2* exy;                // [n_el]: element x, y (lateral offsets are taken from the lines)
   LineGeom* lines;            // [G]
-  int2* wnd;                  // [n_el]: (lo, hi)
-  int* flg;                   // [n_el]: bit 0 needed, bit 1 staged
+  int2* wnd;                  // [n_el]: (lo | flags, hi); lo a multiple of 4, flags bit 0 needed,
+                              // bit 1 staged
+  int* flg;                   // [(n_el + 3) / 4]: the flags, a byte per element, while they are built
 };
 
 // two staging buffers, each followed by an all-zero frame vector (kept zero for the whole
@@ -111,8 +114,8 @@ __host__ __device__ constexpr size_t window_bytes() {
 
 template <int G, int FS>
 __host__ __device__ inline size_t tile_lds_bytes(int n_el) {
-  return window_bytes<G, FS>() + size_t(G) * n_el * sizeof(float4) + G * sizeof(LineGeom) +
-         size_t(n_el) * (sizeof(int2) + sizeof(int));
+  return window_bytes<G, FS>() + size_t(G + 1) * n_el * sizeof(float2) + G * sizeof(LineGeom) +
+         size_t(n_el) * sizeof(int2) + size_t((n_el + 3) / 4) * sizeof(int);
 }
 
 template <int G, int FS>
@@ -120,14 +123,15 @@ __device__ inline TileLds<G, FS> carve(unsigned char* base, int n_el) {
   using V = typename FVec<FS>::T;
   TileLds<G, FS> t;
   t.win = reinterpret_cast<V*>(base);
-  t.geo = reinterpret_cast<float4*>(base + window_bytes<G, FS>());
-  t.lines = reinterpret_cast<LineGeom*>(t.geo + size_t(G) * n_el);
+  t.geo = reinterpret_cast<float2*>(base + window_bytes<G, FS>());
+  t.exy = t.geo + size_t(G) * n_el;
+  t.lines = reinterpret_cast<LineGeom*>(t.exy + n_el);
   t.wnd = reinterpret_cast<int2*>(t.lines + G);
   t.flg = reinterpret_cast<int*>(t.wnd + n_el);
   return t;
 }
 
-__device__ inline int32_t rule_tap(const DasArgs& a, const LineGeom& L, const float4& E, int j) {
+__device__ inline int32_t rule_tap(const DasArgs& a, const LineGeom& L, const float2& E, int j) {
   const int32_t b = a.depth_start + a.depth_step * j;
   const float r = (float)b * a.h;
   return fast_tap(a, b, small_tx_delay(L, r), E.x, E.y, r, r + r, r * r).i0;
@@ -163,14 +167,14 @@ __device__ inline Items<IPT> chunk_items(const TileLds<G, FS>& t, const TileArgs
     d.dst[it] = -1;
     if (item >= ec * quads || c < 0) continue;
     const int2 wd = t.wnd[e];
-    const int i = wd.x + 4 * q;
-    if (!(t.flg[e] & 2) || i > wd.y) continue;
+    const int i = (wd.x & ~3) + 4 * q;
+    if (!(wd.x & 2) || i > wd.y) continue;
     uint32_t in = 0u;
 #pragma unroll
     for (int s = 0; s < 4; ++s) in |= (i + s >= 0 && i + s < S) ? (1u << s) : 0u;
     const int ic = VEC ? (in ? i : 0) : i;  // VEC: all four inside or all outside
     d.voff[it] = uint32_t((size_t(e) * S + (ic < 0 ? 0 : ic)) * sizeof(int16_t));
-    d.dst[it] = (k * ta.span + (ta.pshift ? 2 * q : 4 * q)) | int(in << 26);
+    d.dst[it] = (k * ta.span + ((FS > 1 && ta.pshift) ? 2 * q : 4 * q)) | int(in << 26);
   }
   return d;
 }
@@ -236,7 +240,7 @@ __device__ inline void store_stage(const Prefetch<VEC, FS, IPT>& pf, const Items
       FVec<FS>::set(x[3], f, hi16(dy));
     }
     V* w = win + (dst & kDstMask);
-    if (pshift) {
+    if (FS > 1 && pshift) {
       w[0] = x[0];
       w[1] = x[2];
       w[half] = x[1];
@@ -298,43 +302,44 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
   }
   for (int e = tid; e < a.n_el; e += kDasThreads) {
     t.wnd[e] = make_int2(INT_MAX, INT_MIN);
-    t.flg[e] = 0;
+    t.exy[e] = make_float2(a.el_pos[3 * e], a.el_pos[3 * e + 1]);
   }
-  __syncthreads();
-  for (int idx = tid; idx < a.n_el * G; idx += kDasThreads) {
-    const int gg = idx / a.n_el, e = idx - gg * a.n_el;
-    const ElemGeom E = elem_geom(a, t.lines[gg], e);
-    t.geo[gg * a.n_el + e] = make_float4(E.A, E.B, E.dx, E.dy);
-  }
+  for (int e = tid; e < (a.n_el + 3) / 4; e += kDasThreads) t.flg[e] = 0;
   __syncthreads();
   {
     const float r_last = (float)(a.depth_start + a.depth_step * j_last) * a.h;
     for (int idx = tid; idx < a.n_el * G; idx += kDasThreads) {
       const int gg = idx / a.n_el, e = idx - gg * a.n_el;
       const LineGeom& Lg = t.lines[gg];
+      const ElemGeom E = elem_geom(a, Lg, e);
+      const float2 E2 = make_float2(E.A, E.B);
+      t.geo[gg * a.n_el + e] = E2;
       if (l0 + gg >= a.n_lines || Lg.tx < 0) continue;
-      const float4 E4 = t.geo[gg * a.n_el + e];
-      const ElemGeom E{E4.x, E4.y, E4.z, E4.w};
       if (!in_aperture(a, E, r_last)) continue;
+      const int shift = 8 * (e & 3);
       if (Lg.tx != t_grp) {
-        atomicOr(&t.flg[e], 1);
+        atomicOr(&t.flg[e >> 2], 1 << shift);
         continue;
       }
-      atomicMin(&t.wnd[e].x, rule_tap(a, Lg, E4, j_first));
-      atomicMax(&t.wnd[e].y, rule_tap(a, Lg, E4, j_last) + 1);
-      atomicOr(&t.flg[e], 3);
+      atomicMin(&t.wnd[e].x, rule_tap(a, Lg, E2, j_first));
+      atomicMax(&t.wnd[e].y, rule_tap(a, Lg, E2, j_last) + 1);
+      atomicOr(&t.flg[e >> 2], 3 << shift);
     }
   }
   __syncthreads();
+  // window start aligned down to 4 samples, flags folded into its two low bits
   for (int e = tid; e < a.n_el; e += kDasThreads) {
-    if (!(t.flg[e] & 2)) continue;
-    const int lo = t.wnd[e].x, hi = t.wnd[e].y;
-    int lo4 = lo >= 0 ? (lo & ~3) : -((-lo + 3) & ~3);   // align down to 4 samples
-    if (hi - lo4 + 1 > ta.span) {                          // wider than the buffer: keep the deep end
-      lo4 = hi + 1 - ta.span;
-      lo4 = lo4 >= 0 ? ((lo4 + 3) & ~3) : -((-lo4) & ~3);
+    const int f = (t.flg[e >> 2] >> (8 * (e & 3))) & 3;
+    int lo4 = 0;
+    if (f & 2) {
+      const int lo = t.wnd[e].x, hi = t.wnd[e].y;
+      lo4 = lo >= 0 ? (lo & ~3) : -((-lo + 3) & ~3);
+      if (hi - lo4 + 1 > ta.span) {  // wider than the buffer: keep the deep end
+        lo4 = hi + 1 - ta.span;
+        lo4 = lo4 >= 0 ? ((lo4 + 3) & ~3) : -((-lo4) & ~3);
+      }
     }
-    t.wnd[e].x = lo4;
+    t.wnd[e].x = lo4 | f;
   }
   __syncthreads();
 
@@ -352,13 +357,13 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
   const size_t frame_stride = size_t(a.n_tx) * tx_block;   // samples per frame
   const int16_t* grp_block = rf + size_t(t_grp < 0 ? 0 : t_grp) * tx_block;
   const int16_t* own_block = rf + size_t(L.tx < 0 ? 0 : L.tx) * tx_block;
-  const float4* geo = t.geo + g * a.n_el;
+  const float2* geo = t.geo + g * a.n_el;
   const int n_chunks = (a.n_el + ta.ec - 1) / ta.ec;
   const int half = ta.span >> 1;
 
   auto chunk_needed = [&](int c) {
     int any = 0;
-    for (int k = 0; k < ta.ec && c * ta.ec + k < a.n_el; ++k) any |= t.flg[c * ta.ec + k];
+    for (int k = 0; k < ta.ec && c * ta.ec + k < a.n_el; ++k) any |= t.wnd[c * ta.ec + k].x & 3;
     return any != 0;
   };
   auto next_chunk = [&](int c) {
@@ -389,15 +394,18 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
   auto make_taps = [&](int c, float& den) {
     Taps T;
     T.slow = 0u;
-    const int e0 = c * ta.ec;
+    // the chunk is the same for every lane: make that visible, so element data comes
+    // through scalar loads
+    const int e0 = __builtin_amdgcn_readfirstlane(c * ta.ec);
 #pragma unroll
     for (int k = 0; k < SH::EC; ++k) {
       T.off0[k] = T.off1[k] = ZERO * int(sizeof(V));
       T.w0[k] = T.w1[k] = 0.0f;
       if (k >= ta.ec) continue;
       const int e = min(e0 + k, a.n_el - 1);
-      const float4 E4 = geo[e];
-      const ElemGeom E{E4.x, E4.y, E4.z, E4.w};
+      const float2 E2 = geo[e];
+      const float2 xy = t.exy[e];
+      const ElemGeom E{E2.x, E2.y, xy.x - L.olx, xy.y - L.oly};
       const bool act = lane_ok && e0 + k < a.n_el && in_aperture(a, E, r);
       if (!__any(act)) continue;  // no lane of the wave needs this element
       const float w = act ? apod_weight(a.window, a.array_dims, E.dx, E.dy, inv_w) : 0.0f;
@@ -408,11 +416,12 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
       T.w1[k] = ok ? wp : 0.0f;
       T.w0[k] = ok ? w - wp : 0.0f;
       const int2 wd = t.wnd[e];
-      const int rel = tp.i0 - wd.x;
-      const bool in_win = on_grp && (t.flg[e] & 2) && rel >= 0 && tp.i0 + 1 <= wd.y && rel + 1 < ta.span;
+      const int rel = tp.i0 - (wd.x & ~3);
+      const bool in_win = on_grp && (wd.x & 2) && rel >= 0 && tp.i0 + 1 <= wd.y && rel + 1 < ta.span;
       const int wbase = k * ta.span;
-      const int p0 = ta.pshift ? ((rel & 1) * half + (rel >> 1)) : rel;
-      const int p1 = ta.pshift ? (((rel + 1) & 1) * half + ((rel + 1) >> 1)) : rel + 1;
+      const bool split = FS > 1 && ta.pshift;
+      const int p0 = split ? ((rel & 1) * half + (rel >> 1)) : rel;
+      const int p1 = split ? (((rel + 1) & 1) * half + ((rel + 1) >> 1)) : rel + 1;
       // byte offsets within a buffer
       T.off0[k] = ((ok && in_win) ? wbase + p0 : ZERO) * int(sizeof(V));
       T.off1[k] = ((ok && in_win) ? wbase + p1 : ZERO) * int(sizeof(V));
@@ -425,8 +434,8 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
     const int e0 = c * ta.ec;
     for (int k = 0; k < ta.ec; ++k) {
       if (!(T.slow & (1u << k))) continue;
-      const float4 E4 = geo[e0 + k];
-      const Tap tp = fast_tap(a, b, dtx, E4.x, E4.y, r, r2, rr);
+      const float2 E2 = geo[e0 + k];
+      const Tap tp = fast_tap(a, b, dtx, E2.x, E2.y, r, r2, rr);
       const int16_t* p = own_block + size_t(e0 + k) * S + tp.i0;
       float sw0 = 0.0f, sw1 = 0.0f;
 #pragma unroll
