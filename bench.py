@@ -344,7 +344,7 @@ def run_stream(args, dev):
                    "matrix_volumes": sum(g.array_dims == 2 for g in gs), "dyn_range_db": 50},
         "items_per_s": len(gs) / (step_ms * 1e-3),
         "graph_ms": graph_ms,
-        "autotuned_shape": {"groups_per_cu": shape[0], "cost_order": shape[1]},
+        "autotuned_shape": shape,
         "max_abs_diff_vs_per_call": worst,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,

@@ -294,6 +294,21 @@ typedef struct usbf_batch_item {
 typedef struct usbf_batch_plan usbf_batch_plan;
 
 /*
+ * Launch shape of a plan (what usbf_autotune searches):
+ *   groups_per_cu    workgroups per compute unit of the persistent launch, 1..8
+ *   cost_order       1: work units of the most expensive items (most elements) first
+ *   multi_line_tile  lines per tile for items with >= 4 lines per transmit: 4 (the lines of a
+ *                    transmit share their staged channel data) or 1
+ *   chunk_div        elements per chunk = the tile's largest chunk / chunk_div, 1..8
+ */
+typedef struct usbf_batch_shape {
+  int32_t groups_per_cu;
+  int32_t cost_order;
+  int32_t multi_line_tile;
+  int32_t chunk_div;
+} usbf_batch_shape;
+
+/*
  * Validates the items, uploads their descriptors, orders the work units (most expensive
  * items first), and captures the graph on `stream`.  tune_cache: path of a JSON file written
  * by usbf_autotune (NULL or missing entry: default launch shape).  The plan owns a few KB of
@@ -301,15 +316,19 @@ typedef struct usbf_batch_plan usbf_batch_plan;
  */
 int usbf_batch_plan_create(const usbf_batch_item* items, int32_t n_items, const char* tune_cache,
                            usbf_batch_plan** plan, hipStream_t stream);
+/* The same with an explicit launch shape (EINVAL for a shape outside the ranges above). */
+int usbf_batch_plan_create_shaped(const usbf_batch_item* items, int32_t n_items, const usbf_batch_shape* shape,
+                                  usbf_batch_plan** plan, hipStream_t stream);
 int usbf_batch_run(usbf_batch_plan* plan, hipStream_t stream);
 int usbf_batch_plan_destroy(usbf_batch_plan* plan);
-/* Launch shape chosen for the plan: workgroups per compute unit and ordering (1 = by cost). */
-int usbf_batch_plan_shape(const usbf_batch_plan* plan, int32_t* groups_per_cu, int32_t* cost_order);
+/* Launch shape of the plan. */
+int usbf_batch_plan_shape(const usbf_batch_plan* plan, usbf_batch_shape* shape);
 
 /*
- * Times the batch with every candidate launch shape (workgroups per compute unit x unit
- * ordering) by graph replays and records the fastest in the JSON file `tune_cache`, keyed by
- * the device architecture and a signature of the item sizes.  Synchronises `stream`.
+ * Times the batch with every candidate launch shape (workgroups per compute unit 1..4 x
+ * multi-line tile 4 or 1 x chunk divisor 1 or 2, cost order) by graph replays and records the
+ * fastest in the JSON file `tune_cache`, keyed by the device architecture and a signature of
+ * the item sizes.  Synchronises `stream`.
  */
 int usbf_autotune(const usbf_batch_item* items, int32_t n_items, const char* tune_cache, hipStream_t stream);
 

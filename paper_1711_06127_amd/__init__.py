@@ -51,6 +51,10 @@ class CBatchItem(ctypes.Structure):
                 ("lines", P), ("row_max", P), ("image", P)]
 
 
+class CBatchShape(ctypes.Structure):
+    _fields_ = [("groups_per_cu", I32), ("cost_order", I32), ("multi_line_tile", I32), ("chunk_div", I32)]
+
+
 # name -> (restype, argtypes)
 _SIGS = {
     "usbf_beamform": (I32, [P, I32, P, P, P, P]),
@@ -74,7 +78,8 @@ _SIGS = {
     "usbf_batch_plan_create": (I32, [P, I32, ctypes.c_char_p, P, P]),
     "usbf_batch_run": (I32, [P, P]),
     "usbf_batch_plan_destroy": (I32, [P]),
-    "usbf_batch_plan_shape": (I32, [P, P, P]),
+    "usbf_batch_plan_create_shaped": (I32, [P, I32, P, P, P]),
+    "usbf_batch_plan_shape": (I32, [P, P]),
     "usbf_autotune": (I32, [P, I32, ctypes.c_char_p, P]),
     "usbf_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "usbf_last_error_detail": (ctypes.c_char_p, []),
@@ -408,7 +413,8 @@ class BatchPlan:
     rf tensors in place and call ``run()``.
     """
 
-    def __init__(self, items, dyn_range_db: float = 50.0, tune_cache: str | None = None, autotune: bool = False):
+    def __init__(self, items, dyn_range_db: float = 50.0, tune_cache: str | None = None, autotune: bool = False,
+                 shape: dict | None = None):
         self._plan = None
         self.rf, self.dgs, self.lines, self.row_max, self.images = [], [], [], [], []
         arr = (CBatchItem * len(items))()
@@ -435,13 +441,18 @@ class BatchPlan:
                 raise ValueError("autotune needs a tune_cache path")
             _check(lib().usbf_autotune(arr, len(items), cache, _stream(self.device)))
         plan = ctypes.c_void_p()
-        _check(lib().usbf_batch_plan_create(arr, len(items), cache, ctypes.byref(plan), _stream(self.device)))
+        if shape is not None:
+            cs = CBatchShape(**shape)
+            _check(lib().usbf_batch_plan_create_shaped(arr, len(items), ctypes.byref(cs), ctypes.byref(plan),
+                                                       _stream(self.device)))
+        else:
+            _check(lib().usbf_batch_plan_create(arr, len(items), cache, ctypes.byref(plan), _stream(self.device)))
         self._plan = plan
 
-    def shape(self):
-        g, o = ctypes.c_int32(), ctypes.c_int32()
-        _check(lib().usbf_batch_plan_shape(self._plan, ctypes.byref(g), ctypes.byref(o)))
-        return g.value, o.value
+    def shape(self) -> dict:
+        cs = CBatchShape()
+        _check(lib().usbf_batch_plan_shape(self._plan, ctypes.byref(cs)))
+        return {k: getattr(cs, k) for k, _ in CBatchShape._fields_}
 
     def run(self):
         _check(lib().usbf_batch_run(self._plan, _stream(self.device)))

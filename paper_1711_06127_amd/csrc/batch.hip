@@ -26,7 +26,8 @@ struct usbf_batch_plan {
   BatchItemDev* d_items = nullptr;
   int* d_counter = nullptr;
   float* d_frame = nullptr;  // per-item frame maxima for the log compression (64 floats each)
-  int n_items = 0, total_units = 0, grid = 0, groups_per_cu = 2, cost_order = 1;
+  int n_items = 0, total_units = 0, grid = 0;
+  usbf_batch_shape shape{};
   size_t lds = 0;
   bool vec = true;
   hipGraph_t graph = nullptr;
@@ -79,7 +80,8 @@ std::string batch_key(const usbf_batch_item* items, int n) {
   return arch + "/" + buf;
 }
 
-// The cache is a flat JSON object: {"<key>": {"groups_per_cu": g, "cost_order": c, "ms": t}, ...}
+// The cache is a flat JSON object:
+//   {"<key>": {"groups_per_cu": g, "cost_order": c, "multi_line_tile": t, "chunk_div": d, "ms": ms}, ...}
 std::map<std::string, std::string> read_cache(const char* path) {
   std::map<std::string, std::string> m;
   if (!path) return m;
@@ -120,12 +122,25 @@ int write_cache(const char* path, const std::map<std::string, std::string>& m) {
   return USBF_OK;
 }
 
-int make_plan(const usbf_batch_item* items, int n, int groups_per_cu, int cost_order, usbf_batch_plan** out,
+int check_shape(const usbf_batch_shape& s) {
+  USBF_REQUIRE(s.groups_per_cu >= 1 && s.groups_per_cu <= 8, USBF_EINVAL, "groups_per_cu %d outside 1..8",
+               s.groups_per_cu);
+  USBF_REQUIRE(s.cost_order == 0 || s.cost_order == 1, USBF_EINVAL, "cost_order must be 0 or 1");
+  USBF_REQUIRE(s.multi_line_tile == 1 || s.multi_line_tile == 4, USBF_EINVAL, "multi_line_tile must be 1 or 4");
+  USBF_REQUIRE(s.chunk_div >= 1 && s.chunk_div <= 8, USBF_EINVAL, "chunk_div %d outside 1..8", s.chunk_div);
+  return USBF_OK;
+}
+
+constexpr usbf_batch_shape kDefaultShape = {2, 1, 4, 1};
+
+int make_plan(const usbf_batch_item* items, int n, const usbf_batch_shape& shape, usbf_batch_plan** out,
               hipStream_t user_stream) {
   (void)user_stream;
   USBF_REQUIRE(items && out, USBF_EINVAL, "null items or plan");
   USBF_REQUIRE(n >= 1 && n <= 65536, USBF_EINVAL, "n_items %d out of range", n);
-  USBF_REQUIRE(groups_per_cu >= 1 && groups_per_cu <= 8, USBF_EINVAL, "groups per CU out of range");
+  int st0 = check_shape(shape);
+  if (st0) return st0;
+  const int groups_per_cu = shape.groups_per_cu, cost_order = shape.cost_order;
   std::vector<BatchItemDev> dev(n);
   bool vec = true;
   int max_el[2] = {0, 0};  // largest element count among 1-line and 4-line items
@@ -144,9 +159,9 @@ int make_plan(const usbf_batch_item* items, int n, int groups_per_cu, int cost_o
     USBF_REQUIRE(envelope_length_ok(it.rx.n_depth), USBF_EUNSUPPORTED, "item %d: n_depth %d", i, it.rx.n_depth);
     USBF_REQUIRE(finite_pos(it.dyn_range_db), USBF_EINVAL, "item %d: dyn_range_db", i);
     vec = vec && (it.rx.n_samples % 4 == 0) && ((reinterpret_cast<uintptr_t>(it.rf) & 7) == 0);
-    const int G = it.geom.lines_per_tx >= 4 ? 4 : 1;
+    const int G = it.geom.lines_per_tx >= 4 ? shape.multi_line_tile : 1;
     max_el[G == 4] = std::max(max_el[G == 4], it.geom.n_el);
-    st = batch_item_setup(a, G, &dev[i]);
+    st = batch_item_setup(a, G, shape.chunk_div, &dev[i]);
     if (st) return fail(st, "item %d: %s", i, usbf_last_error_detail());
     dev[i].rf = it.rf;
     dev[i].out = it.lines;
@@ -172,8 +187,7 @@ int make_plan(const usbf_batch_item* items, int n, int groups_per_cu, int cost_o
   p->items.assign(items, items + n);
   p->n_items = n;
   p->total_units = int(units);
-  p->groups_per_cu = groups_per_cu;
-  p->cost_order = cost_order;
+  p->shape = shape;
   p->lds = lds;
   p->vec = vec;
   int dev_id = 0, n_cu = 0;
@@ -227,14 +241,17 @@ extern "C" int usbf_batch_plan_create(const usbf_batch_item* items, int32_t n_it
                                       usbf_batch_plan** plan, hipStream_t stream) {
   USBF_REQUIRE(items && plan, USBF_EINVAL, "null items or plan");
   USBF_REQUIRE(n_items >= 1, USBF_EINVAL, "empty batch");
-  int gpc = 2, order = 1;
+  usbf_batch_shape shape = kDefaultShape;
   const auto cache = read_cache(tune_cache);
   const auto it = cache.find(batch_key(items, n_items));
   if (it != cache.end()) {
-    gpc = std::min(8, std::max(1, json_int(it->second, "groups_per_cu", gpc)));
-    order = json_int(it->second, "cost_order", order) ? 1 : 0;
+    shape.groups_per_cu = json_int(it->second, "groups_per_cu", shape.groups_per_cu);
+    shape.cost_order = json_int(it->second, "cost_order", shape.cost_order);
+    shape.multi_line_tile = json_int(it->second, "multi_line_tile", shape.multi_line_tile);
+    shape.chunk_div = json_int(it->second, "chunk_div", shape.chunk_div);
+    if (check_shape(shape)) return fail(USBF_EINVAL, "tune cache %s: invalid entry", tune_cache);
   }
-  return make_plan(items, n_items, gpc, order, plan, stream);
+  return make_plan(items, n_items, shape, plan, stream);
 }
 
 extern "C" int usbf_batch_run(usbf_batch_plan* plan, hipStream_t stream) {
@@ -249,49 +266,65 @@ extern "C" int usbf_batch_plan_destroy(usbf_batch_plan* plan) {
   return USBF_OK;
 }
 
-extern "C" int usbf_batch_plan_shape(const usbf_batch_plan* plan, int32_t* groups_per_cu, int32_t* cost_order) {
-  USBF_REQUIRE(plan && groups_per_cu && cost_order, USBF_EINVAL, "null argument");
-  *groups_per_cu = plan->groups_per_cu;
-  *cost_order = plan->cost_order;
+extern "C" int usbf_batch_plan_create_shaped(const usbf_batch_item* items, int32_t n_items,
+                                             const usbf_batch_shape* shape, usbf_batch_plan** plan,
+                                             hipStream_t stream) {
+  USBF_REQUIRE(items && plan && shape, USBF_EINVAL, "null items, shape or plan");
+  USBF_REQUIRE(n_items >= 1, USBF_EINVAL, "empty batch");
+  return make_plan(items, n_items, *shape, plan, stream);
+}
+
+extern "C" int usbf_batch_plan_shape(const usbf_batch_plan* plan, usbf_batch_shape* shape) {
+  USBF_REQUIRE(plan && shape, USBF_EINVAL, "null argument");
+  *shape = plan->shape;
   return USBF_OK;
 }
 
 extern "C" int usbf_autotune(const usbf_batch_item* items, int32_t n_items, const char* tune_cache,
                              hipStream_t stream) {
   USBF_REQUIRE(items && tune_cache, USBF_EINVAL, "null items or cache path");
+  USBF_REQUIRE(n_items >= 1, USBF_EINVAL, "empty batch");
+  bool any_multi = false;
+  for (int i = 0; i < n_items; ++i) any_multi = any_multi || items[i].geom.lines_per_tx >= 4;
+  std::vector<usbf_batch_shape> cands;
+  for (int tile : {4, 1}) {
+    if (tile == 1 && !any_multi) continue;  // the same plan as tile 4
+    for (int div : {1, 2})
+      for (int g = 1; g <= 4; ++g) cands.push_back({g, 1, tile, div});
+  }
   float best_ms = 1e30f;
-  int best_g = 2, best_o = 1;
+  usbf_batch_shape best = kDefaultShape;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return fail(USBF_EDEVICE, "event creation failed");
   int st = USBF_OK;
-  for (int order = 1; order >= 0 && !st; --order) {
-    for (int g = 1; g <= 4 && !st; ++g) {
-      usbf_batch_plan* p = nullptr;
-      st = make_plan(items, n_items, g, order, &p, stream);
-      if (st) break;
-      for (int w = 0; w < 2 && !st; ++w) st = usbf_batch_run(p, stream);
-      const int reps = 5;
-      (void)hipEventRecord(e0, stream);
-      for (int r = 0; r < reps && !st; ++r) st = usbf_batch_run(p, stream);
-      (void)hipEventRecord(e1, stream);
-      float ms = 0.0f;
-      if (!st && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-        st = fail(USBF_EDEVICE, "timing failed");
-      destroy(p);
-      if (!st && ms / reps < best_ms) {
-        best_ms = ms / reps;
-        best_g = g;
-        best_o = order;
-      }
+  for (const usbf_batch_shape& c : cands) {
+    usbf_batch_plan* p = nullptr;
+    st = make_plan(items, n_items, c, &p, stream);
+    if (st) break;
+    for (int w = 0; w < 2 && !st; ++w) st = usbf_batch_run(p, stream);
+    const int reps = 5;
+    (void)hipEventRecord(e0, stream);
+    for (int r = 0; r < reps && !st; ++r) st = usbf_batch_run(p, stream);
+    (void)hipEventRecord(e1, stream);
+    float ms = 0.0f;
+    if (!st && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      st = fail(USBF_EDEVICE, "timing failed");
+    destroy(p);
+    if (st) break;
+    if (ms / reps < best_ms) {
+      best_ms = ms / reps;
+      best = c;
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st) return st;
   auto cache = read_cache(tune_cache);
-  char val[160];
-  snprintf(val, sizeof val, "{\"groups_per_cu\": %d, \"cost_order\": %d, \"ms\": %.4f}", best_g, best_o, best_ms);
+  char val[200];
+  snprintf(val, sizeof val,
+           "{\"groups_per_cu\": %d, \"cost_order\": %d, \"multi_line_tile\": %d, \"chunk_div\": %d, \"ms\": %.4f}",
+           best.groups_per_cu, best.cost_order, best.multi_line_tile, best.chunk_div, best_ms);
   cache[batch_key(items, n_items)] = val;
   return write_cache(tune_cache, cache);
 }

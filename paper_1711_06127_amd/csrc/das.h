@@ -23,8 +23,9 @@ struct BatchItemDev {
   int n_units;        // (lines / G) * depth tiles
 };
 
-// Fills the tiling of an item for tiles of G lines (G = 1 or 4), one frame per block.
-int batch_item_setup(const DasArgs& a, int G, BatchItemDev* it);
+// Fills the tiling of an item for tiles of G lines (G = 1 or 4), one frame per block, with
+// the tile's largest element chunk divided by chunk_div.
+int batch_item_setup(const DasArgs& a, int G, int chunk_div, BatchItemDev* it);
 // LDS bytes the persistent kernel needs for 1-line tiles of up to max_n_el_g1 elements and
 // 4-line tiles of up to max_n_el_g4 elements (0: no such tiles).
 size_t persistent_lds_bytes(int max_n_el_g1, int max_n_el_g4);

@@ -709,11 +709,13 @@ static TileArgs single_frame_tiles(const DasArgs& a) {
   return ta;
 }
 
-int batch_item_setup(const DasArgs& a, int G, BatchItemDev* it) {
+int batch_item_setup(const DasArgs& a, int G, int chunk_div, BatchItemDev* it) {
   USBF_REQUIRE(G == 1 || G == 4, USBF_EUNSUPPORTED, "batched tiles group 1 or 4 lines");
+  USBF_REQUIRE(chunk_div >= 1, USBF_EINVAL, "chunk_div must be >= 1");
   it->a = a;
   it->G = G;
   it->ta = G == 4 ? single_frame_tiles<4>(a) : single_frame_tiles<1>(a);
+  it->ta.ec = std::max(1, it->ta.ec / chunk_div);
   const int64_t units = int64_t((a.n_lines + G - 1) / G) * it->ta.n_dtiles;
   USBF_REQUIRE(units < (int64_t(1) << 30), USBF_EUNSUPPORTED, "too many tiles");
   it->n_units = int(units);

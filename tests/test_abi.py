@@ -165,6 +165,10 @@ def test_batch_plan_rejects(u):
     assert L.usbf_batch_plan_create(bad, 2, None, ctypes.byref(plan), None) == -3      # envelope length
     assert L.usbf_batch_run(None, None) == -1
     assert L.usbf_batch_plan_destroy(None) == 0
-    g, o = ctypes.c_int32(), ctypes.c_int32()
-    assert L.usbf_batch_plan_shape(None, ctypes.byref(g), ctypes.byref(o)) == -1
+    sh = u.CBatchShape()
+    assert L.usbf_batch_plan_shape(None, ctypes.byref(sh)) == -1
+    for bad_shape in [(0, 1, 4, 1), (9, 1, 4, 1), (2, 2, 4, 1), (2, 1, 2, 1), (2, 1, 4, 0), (2, 1, 4, 9)]:
+        sh = u.CBatchShape(*bad_shape)
+        assert L.usbf_batch_plan_create_shaped(arr, 1, ctypes.byref(sh), ctypes.byref(plan), None) == -1, bad_shape
+    assert L.usbf_batch_plan_create_shaped(arr, 1, None, ctypes.byref(plan), None) == -1
     assert L.usbf_autotune(arr, 1, None, None) == -1

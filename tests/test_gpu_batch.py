@@ -114,8 +114,24 @@ def test_autotune_writes_cache_and_plan_reads_it(usbf, mixed, tmp_path):
     assert len(entries) == 1
     (key, val), = entries.items()
     assert key.startswith("gfx950")
-    assert plan.shape() == (val["groups_per_cu"], val["cost_order"])
+    assert plan.shape() == {k: val[k] for k in ("groups_per_cu", "cost_order", "multi_line_tile", "chunk_div")}
     assert val["ms"] > 0
+    plan.run()
+    torch.cuda.synchronize()
+    for rf, dg, img in zip(rfs[:2], dgs[:2], plan.images):
+        ref = usbf.bmode(rf.unsqueeze(0), dg, 50.0)[0]
+        assert (img - ref).abs().max().item() <= 1e-5
+    plan.close()
+
+
+@pytest.mark.parametrize("tile,div,gpc", [(4, 1, 1), (1, 1, 3), (4, 2, 2), (1, 2, 4)])
+def test_every_launch_shape_gives_the_same_images(usbf, mixed, tile, div, gpc):
+    """Tile height, element-chunk size and launch size change only the schedule: the images stay
+    those of the per-call pipeline."""
+    gs, rfs, dgs = mixed
+    shape = {"groups_per_cu": gpc, "cost_order": 1, "multi_line_tile": tile, "chunk_div": div}
+    plan = usbf.BatchPlan([(rfs[0], dgs[0]), (rfs[1], dgs[1])], 50.0, shape=shape)
+    assert plan.shape() == shape
     plan.run()
     torch.cuda.synchronize()
     for rf, dg, img in zip(rfs[:2], dgs[:2], plan.images):
