@@ -126,6 +126,22 @@ def test_beamform_volume_subset(usbf):
     assert rel_err(y.cpu().numpy(), ref) <= TOL
 
 
+def test_beamform_full_volume_sampled(usbf):
+    """The whole 3D workload (1024 steered lines, 1024 elements, 2000 samples) in the launch the
+    benchmark times, checked against the oracle on sampled voxels of every line block."""
+    g = synth.config_volume_3d()
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(11)
+    rf = torch.randint(-3000, 3000, (1, g.n_tx, g.n_el, g.n_samples), dtype=torch.int16, device="cuda", generator=gen)
+    dg = usbf.DeviceGeometry(g)
+    y = usbf.beamform(rf, dg).cpu().numpy()
+    rng = np.random.default_rng(11)
+    m = 3000
+    pix = np.stack([np.zeros(m, np.int64), rng.integers(0, g.n_lines, m), rng.integers(0, g.n_depth, m)], 1)
+    ref = oracle.das(g, rf.cpu().numpy(), pix)
+    assert rel_err(y[pix[:, 0], pix[:, 1], pix[:, 2]], ref) <= TOL
+
+
 def test_beamform_edge_cases(usbf):
     """Ragged depth count, a transmit index out of range (zero line), a depth grid starting at
     sample 0 (empty aperture except the element under the line), rectangular window, t0 != 0."""
