@@ -7,7 +7,10 @@ receive lines each, 4096 int16 samples per channel at 40 MHz, 2048 output sample
 path.  Inputs are synthetic phantoms (20 points + 5000 speckle scatterers, 40 dB SNR) already
 resident in HBM when the timed region starts.
 
-Prints one JSON line (see the design doc for the fields).
+Prints one JSON line: metric, value (pixel·channel samples per second over the timed steps),
+stage times, the delay-and-sum roofline (algorithmic bytes over the event-timed launch, against
+8 TB/s, with the HBM traffic counted by rocprofv3 when it matches the source) and the CPU
+oracle's rate on a bounded sample.
 """
 from __future__ import annotations
 

@@ -144,7 +144,7 @@ int usbf_beamform(const int16_t* rf, int32_t n_frames, const usbf_geometry* geom
 
 /*
  * Envelope detection (Sec. 1 pipeline list, "envelope detection"; the Hilbert-transform
- * envelope of the PSF study, Sec. 4): for each of n_rows rows of length n,
+ * envelope of the PSF study, Sec. 3.2): for each of n_rows rows of length n,
  *   env = | IDFT( H . DFT(in) ) |,  H[0] = 1, H[k] = 2 for 0 < k < n/2, H[n/2] = 1 (n even),
  *   H[k] = 0 otherwise (circular, no padding).
  *   in, env  float [n_rows][n]  (in == env allowed: in place)
@@ -270,8 +270,8 @@ int usbf_beamform_weighted(const float* x, const float* w, const float* y_fallba
  * A batch of frames and volumes of different sizes, taken through the whole pipeline
  * (delay and sum -> envelope -> log compression -> scan conversion) by one persistent
  * delay-and-sum launch followed by the per-item epilogues, captured once in a HIP graph and
- * replayed by usbf_batch_run.  For streams of acquisitions whose geometry repeats (Sec. 4
- * runs every acquisition through the same node graph).
+ * replayed by usbf_batch_run.  For streams of acquisitions whose geometry repeats (the
+ * paper runs every acquisition through the same node graph, Sec. 2).
  *   rf       int16 [n_tx][n_el][n_samples], one frame or volume
  *   lines    float [n_lines][n_depth], receives the beamformed lines, then their envelope
  *   row_max  float [n_lines]

@@ -94,7 +94,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with python paper_1711_06127_amd/build.py "
                                "or python paper_1711_06127_amd/build.py")
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():

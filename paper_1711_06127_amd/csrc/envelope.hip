@@ -1,5 +1,5 @@
 // Envelope detection (Sec. 1 pipeline list; Hilbert-transform envelope of the PSF study,
-// Sec. 4): env = |IDFT(H . DFT(y))| per row, H keeping DC (and Nyquist), doubling the
+// Sec. 3.2): env = |IDFT(H . DFT(y))| per row, H keeping DC (and Nyquist), doubling the
 // positive and removing the negative frequencies.
 //
 // One workgroup owns a row at a time (grid-stride over rows so the twiddle table is built

@@ -6,8 +6,8 @@ beamforming, envelope, compression or interpolation arithmetic; both the CPU
 oracle and the GPU library receive the same arrays.
 
 The paper's evaluation hardware (a 128-element, 0.3 mm pitch linear array and a
-32x32 matrix probe, Sec. 3 "Comparison" and Sec. 3.2) motivates the layouts; the
-exact numbers are the workload definitions stated in the design doc.
+32x32 matrix probe, Sec. 3 and its run-time Table 1) motivates the layouts; the
+exact numbers are those of the config_* functions below.
 """
 from __future__ import annotations
 

@@ -2,7 +2,7 @@
 
 Point targets plus uniformly scattered speckle with Gaussian amplitudes, and
 optional anechoic cysts, for the 2D linear and 3D matrix workloads.  The paper
-images a wire target for its point-spread-function study (Sec. 4 "PSF"); here
+images a wire target for its point-spread-function study (Sec. 3.2); here
 point targets are placed on the beamformer's own pixel grid so that a correct
 beamformer peaks exactly on them.
 """

@@ -1,6 +1,6 @@
 """Pins of the oracle's envelope detection, log compression and scan conversion
 (Sec. 1 pipeline list; Sec. 2 method list items 3-5; the PSF study's Hilbert envelope and
-50 dB display range in Sec. 4)."""
+50 dB display range in Sec. 3.2)."""
 import numpy as np
 import pytest
 import scipy.signal
