@@ -155,6 +155,22 @@ int usbf_envelope(const float* in, int64_t n_rows, int32_t n, float* env, float*
                   hipStream_t stream);
 
 /*
+ * Envelope by IQ demodulation with frequency compounding (Sec. 2 method list item 3, the
+ * paper's own envelope node): each row is mixed down to baseband for every band k, low-passed
+ * and its magnitude taken; the bands are averaged:
+ *   env[n] = (2 / K) sum_k | sum_m g_k[m] in[n + c - m] |,  g_k[m] = h[m] exp(2 pi i f_k (m - c) / fs)
+ * (mixing and low-passing, up to a unit-magnitude phase), with h the Hamming-windowed sinc of
+ * n_taps = 2c + 1 taps, cutoff bandwidth / 2, unit gain at DC; samples outside the row are 0.
+ * A tone of amplitude A at a band's centre has envelope A.
+ *   in, env   float [n_rows][n] device (in != env), 8 <= n <= 8192
+ *   freqs     host float [n_bands], 0 < f_k < fs / 2;  1 <= n_bands <= 4
+ *   n_taps    odd, 3..127;  0 < bandwidth <= fs
+ *   row_max   float [n_rows] maximum of each env row, or NULL.
+ */
+int usbf_envelope_iq(const float* in, int64_t n_rows, int32_t n, float fs, const float* freqs, int32_t n_bands,
+                     float bandwidth, int32_t n_taps, float* env, float* row_max, hipStream_t stream);
+
+/*
  * Log compression to a display range (Sec. 1 pipeline list; Sec. 2 method list item 4):
  *   out = clamp(1 + (20 / dyn_range_db) log10(env / ref), 0, 1),  out = 0 where env <= 0,
  * with ref the given reference, or when ref <= 0 the maximum of each frame.

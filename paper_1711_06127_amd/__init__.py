@@ -59,6 +59,7 @@ class CBatchShape(ctypes.Structure):
 _SIGS = {
     "usbf_beamform": (I32, [P, I32, P, P, P, P]),
     "usbf_envelope": (I32, [P, I64, I32, P, P, P]),
+    "usbf_envelope_iq": (I32, [P, I64, I32, F32, P, I32, F32, I32, P, P, P]),
     "usbf_log_compress": (I32, [P, I32, I64, F32, F32, P, P, ctypes.c_size_t, P]),
     "usbf_scan_convert": (I32, [P, I32, P, P, P]),
     "usbf_log_scan_convert": (I32, [P, P, I32, P, F32, F32, P, P, ctypes.c_size_t, P]),
@@ -213,6 +214,27 @@ def envelope(x: torch.Tensor, out: torch.Tensor | None = None, row_max=False):
     else:
         rm = torch.empty(x.shape[:-1], dtype=torch.float32, device=x.device) if row_max else None
     _check(lib().usbf_envelope(_ptr(x), rows, n, _ptr(out), _ptr(rm), _stream(x.device)))
+    return (out, rm) if rm is not None else out
+
+
+def envelope_iq(x: torch.Tensor, fs: float, freqs, bandwidth: float, n_taps: int = 63,
+                out: torch.Tensor | None = None, row_max=False):
+    """IQ-demodulation envelope with frequency compounding along the last axis (centre
+    frequencies `freqs` in Hz).  Returns env, or (env, per-row maxima) when row_max is True or a
+    preallocated float32 tensor of x.shape[:-1]."""
+    _need_cuda(x, "x", torch.float32)
+    n = x.shape[-1]
+    rows = x.numel() // n
+    if out is None:
+        out = torch.empty_like(x)
+    if isinstance(row_max, torch.Tensor):
+        _need_cuda(row_max, "row_max", torch.float32)
+        rm = row_max
+    else:
+        rm = torch.empty(x.shape[:-1], dtype=torch.float32, device=x.device) if row_max else None
+    f = (ctypes.c_float * len(freqs))(*[float(v) for v in freqs])
+    _check(lib().usbf_envelope_iq(_ptr(x), rows, n, float(fs), f, len(freqs), float(bandwidth), int(n_taps),
+                                  _ptr(out), _ptr(rm), _stream(x.device)))
     return (out, rm) if rm is not None else out
 
 

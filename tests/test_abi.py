@@ -172,3 +172,19 @@ def test_batch_plan_rejects(u):
         assert L.usbf_batch_plan_create_shaped(arr, 1, ctypes.byref(sh), ctypes.byref(plan), None) == -1, bad_shape
     assert L.usbf_batch_plan_create_shaped(arr, 1, None, ctypes.byref(plan), None) == -1
     assert L.usbf_autotune(arr, 1, None, None) == -1
+
+
+def test_envelope_iq_rejects(u):
+    L = u.lib()
+    f = (ctypes.c_float * 4)(5e6, 4e6, 6e6, 7e6)
+    assert L.usbf_envelope_iq(None, 4, 2048, 40e6, f, 3, 2e6, 63, FAKE, None, None) == -1
+    assert L.usbf_envelope_iq(FAKE, 4, 2048, 40e6, f, 3, 2e6, 63, FAKE, None, None) == -1  # in place
+    assert L.usbf_envelope_iq(FAKE, 0, 2048, 40e6, f, 3, 2e6, 63, FAKE + 64, None, None) == -1
+    assert L.usbf_envelope_iq(FAKE, 4, 4, 40e6, f, 3, 2e6, 63, FAKE + 64, None, None) == -3
+    assert L.usbf_envelope_iq(FAKE, 4, 9000, 40e6, f, 3, 2e6, 63, FAKE + 64, None, None) == -3
+    assert L.usbf_envelope_iq(FAKE, 4, 2048, 40e6, f, 5, 2e6, 63, FAKE + 64, None, None) == -3
+    assert L.usbf_envelope_iq(FAKE, 4, 2048, 40e6, f, 3, 2e6, 64, FAKE + 64, None, None) == -3
+    assert L.usbf_envelope_iq(FAKE, 4, 2048, 40e6, f, 3, 2e6, 129, FAKE + 64, None, None) == -3
+    assert L.usbf_envelope_iq(FAKE, 4, 2048, 40e6, f, 3, 0.0, 63, FAKE + 64, None, None) == -1
+    bad = (ctypes.c_float * 3)(5e6, 25e6, 6e6)
+    assert L.usbf_envelope_iq(FAKE, 4, 2048, 40e6, bad, 3, 2e6, 63, FAKE + 64, None, None) == -1
