@@ -7,9 +7,11 @@
 //
 // One workgroup per row at a time (grid-stride over rows): the taps are built once per
 // workgroup in LDS, the row is staged in LDS with c zeros on either side, and every lane
-// computes R consecutive outputs, sliding a register window along the row so that each tap
-// costs one LDS read of the row shared by all K bands.  Bound by the FMA count, 2 K L per
-// output sample.
+// computes R consecutive outputs.  h is even, so g_k[c - d] = conj(g_k[c + d]) and
+//   z_k[n] = h[c] y[n] + sum_{d=1..c} ( Re g_k[c+d] (y[n-d] + y[n+d]) + i Im g_k[c+d] (y[n-d] - y[n+d]) ),
+// whose sum and difference are shared by all K bands; two register windows slide outwards
+// from the output, one LDS read each per tap pair.  Bound by the arithmetic, K (L + 1) + L - 1
+// operations per output sample.
 #include "common.h"
 
 namespace usbf {
@@ -30,20 +32,21 @@ template <int K>
 __global__ __launch_bounds__(kIqThreads) void envelope_iq_kernel(const float* __restrict__ in, int64_t n_rows, IqArgs a,
                                                                  float* __restrict__ env, float* __restrict__ row_max) {
   extern __shared__ __align__(16) float sm[];
-  float* gre = sm;                        // [K][L]
-  float* gim = gre + K * kIqMaxTaps;      // [K][L]
+  float* gre = sm;                        // [K][c + 1]: Re g_k[c + d]
+  float* gim = gre + K * kIqMaxTaps;      // [K][c + 1]: Im g_k[c + d]
   float* row = gim + K * kIqMaxTaps;      // [n + 2c + kIqOut]
   __shared__ float red[kIqThreads / 64];
   const int tid = threadIdx.x;
   const int L = a.L, c = a.c, n = a.n;
 
-  // ---- taps: prototype, its DC gain, then the K modulated copies
+  // ---- taps: prototype, its DC gain, then the K modulated copies for d = 0 .. c
   const float fc2 = a.bw / a.fs;  // 2 * cutoff in cycles per sample
   float hm = 0.0f;
   if (tid < L) {
-    const float x = float(tid - c);
-    const float s = (tid == c) ? fc2 : sinpif(fc2 * x) / (3.14159265358979323846f * x);
-    const float w = 0.54f - 0.46f * cospif(2.0f * float(tid) / float(L - 1));
+    const int d = tid <= c ? c - tid : tid - c;  // the window is even: use |m - c|
+    const float x = float(d);
+    const float s = (d == 0) ? fc2 : sinpif(fc2 * x) / (3.14159265358979323846f * x);
+    const float w = 0.54f + 0.46f * cospif(x / float(c));  // 0.54 - 0.46 cos(2 pi m / (L - 1))
     hm = s * w;
   }
   float sum = hm;
@@ -51,15 +54,15 @@ __global__ __launch_bounds__(kIqThreads) void envelope_iq_kernel(const float* __
   if ((tid & 63) == 0) red[tid >> 6] = sum;
   __syncthreads();
   const float dc = red[0] + red[1];  // L <= 127 < 128: the first two waves hold every tap
-  if (tid < L) {
+  if (tid >= c && tid < L) {
+    const int d = tid - c;
     const float h = hm / dc;
-    const float x = float(tid - c);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       float sn, cs;
-      sincospif(2.0f * a.f[k] * x / a.fs, &sn, &cs);
-      gre[k * kIqMaxTaps + tid] = h * cs;
-      gim[k * kIqMaxTaps + tid] = h * sn;
+      sincospif(2.0f * a.f[k] * float(d) / a.fs, &sn, &cs);
+      gre[k * kIqMaxTaps + d] = h * cs;
+      gim[k * kIqMaxTaps + d] = h * sn;
     }
   }
   const int padded = n + 2 * c + kIqOut;
@@ -70,29 +73,43 @@ __global__ __launch_bounds__(kIqThreads) void envelope_iq_kernel(const float* __
     __syncthreads();
     float mx = 0.0f;
     for (int n0 = tid * kIqOut; n0 < n; n0 += kIqThreads * kIqOut) {
-      // output n0 + i uses row[(n0 + i) + c - m + c] for m = 0 .. L - 1
+      // y[t] sits at row[t + c]; output n0 + i needs y[n0 + i - d] and y[n0 + i + d]
       float re[K][kIqOut], im[K][kIqOut];
+      float vl[kIqOut], vr[kIqOut];
 #pragma unroll
-      for (int k = 0; k < K; ++k)
+      for (int i = 0; i < kIqOut; ++i) vl[i] = vr[i] = row[n0 + c + i];
 #pragma unroll
-        for (int i = 0; i < kIqOut; ++i) re[k][i] = im[k][i] = 0.0f;
-      // window v[i] = row[n0 + 2c - m + i]: start at m = 0, then slide one sample left per tap
-      float v[kIqOut];
+      for (int k = 0; k < K; ++k) {
+        const float g0 = gre[k * kIqMaxTaps];
 #pragma unroll
-      for (int i = 0; i < kIqOut; ++i) v[i] = row[n0 + 2 * c + i];
-      for (int m = 0; m < L; ++m) {
+        for (int i = 0; i < kIqOut; ++i) {
+          re[k][i] = g0 * vl[i];
+          im[k][i] = 0.0f;
+        }
+      }
+      for (int d = 1; d <= c; ++d) {
+        // slide: vl[i] = y[n0 + i - d] (leftwards), vr[i] = y[n0 + i + d] (rightwards)
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const float gr = gre[k * kIqMaxTaps + m], gi = gim[k * kIqMaxTaps + m];
+        for (int i = kIqOut - 1; i > 0; --i) vl[i] = vl[i - 1];
+        vl[0] = row[n0 + c - d];  // index >= n0 >= 0
 #pragma unroll
-          for (int i = 0; i < kIqOut; ++i) {
-            re[k][i] = __builtin_fmaf(gr, v[i], re[k][i]);
-            im[k][i] = __builtin_fmaf(gi, v[i], im[k][i]);
-          }
+        for (int i = 0; i < kIqOut - 1; ++i) vr[i] = vr[i + 1];
+        vr[kIqOut - 1] = row[n0 + c + kIqOut - 1 + d];  // index < n + 2c + kIqOut
+        float sp[kIqOut], sm_[kIqOut];
+#pragma unroll
+        for (int i = 0; i < kIqOut; ++i) {
+          sp[i] = vl[i] + vr[i];
+          sm_[i] = vl[i] - vr[i];
         }
 #pragma unroll
-        for (int i = kIqOut - 1; i > 0; --i) v[i] = v[i - 1];
-        if (m + 1 < L) v[0] = row[n0 + 2 * c - m - 1];  // index >= n0 >= 0
+        for (int k = 0; k < K; ++k) {
+          const float gr = gre[k * kIqMaxTaps + d], gi = gim[k * kIqMaxTaps + d];
+#pragma unroll
+          for (int i = 0; i < kIqOut; ++i) {
+            re[k][i] = __builtin_fmaf(gr, sp[i], re[k][i]);
+            im[k][i] = __builtin_fmaf(gi, sm_[i], im[k][i]);
+          }
+        }
       }
       float* e = env + r * n;
 #pragma unroll
