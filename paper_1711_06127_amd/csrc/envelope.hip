@@ -180,6 +180,126 @@ __device__ inline int fft_pow2_from(c32* a, c32* b, const c32* tw, int cur) {
   }
 }
 
+// ---- power-of-two rows with fused ends: the first stage takes its inputs from registers
+// (the prefetched row), the last stage of the forward transform writes the analytic-signal
+// spectrum (weights and conjugation applied), and the last stage of the inverse writes the
+// magnitudes straight to global memory -- three LDS round trips and barriers fewer per row.
+template <int N, int NS>
+__host__ __device__ constexpr int radix_at() {
+  return (N / NS) >= 8 ? 8 : N / NS;
+}
+
+// One Stockham stage with a custom source (element j + r M of the input) and destination.
+template <int N, int NS, typename Load, typename Store>
+__device__ inline void stage_ls(const c32* __restrict__ tw, Load load, Store store) {
+  constexpr int R = radix_at<N, NS>();
+  constexpr int M = N / R, TWS = N / (NS * R);
+  for (int j = threadIdx.x; j < M; j += kEnvThreads) {
+    c32 v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = load(j, r, M);
+    const int k = j % NS;
+    if constexpr (NS > 1) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[pad(r * k * TWS)]);
+    }
+    if constexpr (R == 2) dft2(v);
+    if constexpr (R == 4) dft4(v);
+    if constexpr (R == 8) dft8(v);
+    const int o = (j / NS) * NS * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) store(o + r * NS, v[r]);
+  }
+}
+
+// Stages NS .. N of a transform whose input is in LDS buffer a; every stage but the last
+// writes the other buffer, the last hands its outputs to fin(k, value).
+template <int N, int NS, typename Fin>
+__device__ inline void stages_from(c32* a, c32* b, const c32* tw, Fin fin) {
+  constexpr int R = radix_at<N, NS>();
+  auto from_a = [&](int j, int r, int M) { return a[pad(j + r * M)]; };
+  if constexpr (NS * R == N) {
+    stage_ls<N, NS>(tw, from_a, fin);
+  } else {
+    stage_ls<N, NS>(tw, from_a, [&](int i, c32 v) { b[pad(i)] = v; });
+    __syncthreads();
+    stages_from<N, NS * R>(b, a, tw, fin);
+  }
+}
+
+// the buffer the last stage of a transform starting (at stage NS) in buffer 0 reads
+template <int N, int NS>
+__host__ __device__ constexpr int last_src(int cur) {
+  return (NS * radix_at<N, NS>() == N) ? cur : last_src<N, NS * radix_at<N, NS>()>(cur ^ 1);
+}
+
+template <int N>
+__global__ __launch_bounds__(kEnvThreads) void envelope_pow2_kernel(const float* __restrict__ in, int64_t n_rows,
+                                                                    float* __restrict__ env,
+                                                                    float* __restrict__ row_max) {
+  static_assert(N >= 64 && (N & (N - 1)) == 0 && N <= kMaxEnvelopeLength, "power-of-two length");
+  extern __shared__ c32 lds[];
+  constexpr int np = padded_len(N);
+  constexpr int M1 = N / 8;  // butterflies of the first (radix 8) stage
+  c32* buf0 = lds;
+  c32* buf1 = lds + np;
+  c32* tw = lds + 2 * np;
+  const int tid = threadIdx.x;
+  for (int k = tid; k < N; k += kEnvThreads) {
+    float s, c;
+    sincospif(2.0f * float(k) / float(N), &s, &c);
+    tw[pad(k)] = {c, -s};
+  }
+  __shared__ float red[kEnvThreads / 64];
+  // prefetched row, laid out as the first stage reads it: lane j holds x[j + r N/8]
+  float pre[8];
+  auto load_row = [&](int64_t row) {
+    const float* x = in + row * N;
+    if (tid < M1) {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) pre[r] = x[tid + r * M1];
+    }
+  };
+  if (int64_t(blockIdx.x) < n_rows) load_row(blockIdx.x);
+  __syncthreads();  // twiddles
+  for (int64_t row = blockIdx.x; row < n_rows; row += gridDim.x) {
+    // forward transform: first stage from registers into buf0
+    stage_ls<N, 1>(tw, [&](int, int r, int) { return c32{pre[r], 0.0f}; }, [&](int i, c32 v) { buf0[pad(i)] = v; });
+    if (row + gridDim.x < n_rows) load_row(row + gridDim.x);
+    __syncthreads();
+    // remaining stages; the last writes H X, conjugated (inverse by forward transform), into
+    // the buffer it does not read
+    constexpr int src1 = last_src<N, 8>(0);
+    c32* spec = src1 == 0 ? buf1 : buf0;
+    stages_from<N, 8>(buf0, buf1, tw, [&](int k, c32 v) {
+      const float hk = (k == 0 || k == N / 2) ? 1.0f : (k < N / 2 ? 2.0f : 0.0f);
+      spec[pad(k)] = c32{v.x * hk, -v.y * hk};
+    });
+    __syncthreads();
+    c32* other = spec == buf0 ? buf1 : buf0;
+    stage_ls<N, 1>(tw, [&](int j, int r, int M) { return spec[pad(j + r * M)]; },
+                   [&](int i, c32 v) { other[pad(i)] = v; });
+    __syncthreads();
+    float mx = 0.0f;
+    float* e = env + row * N;
+    stages_from<N, 8>(other, spec, tw, [&](int k, c32 v) {
+      const float m = sqrtf(__builtin_fmaf(v.x, v.x, v.y * v.y)) * (1.0f / float(N));
+      e[k] = m;
+      mx = fmaxf(mx, m);
+    });
+    if (row_max) {
+      for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+      if ((tid & 63) == 0) red[tid >> 6] = mx;
+    }
+    __syncthreads();
+    if (row_max && tid == 0) {
+      float m = red[0];
+      for (int w = 1; w < kEnvThreads / 64; ++w) m = fmaxf(m, red[w]);
+      row_max[row] = m;
+    }
+  }
+}
+
 // Forward FFT of buf[0] (result in buf[0] or buf[1]); returns the buffer holding the result.
 // PRIMES: the plan may hold radices 7 ... 31 (kept out of the common kernel: their register
 // footprint would cut its occupancy).
@@ -342,10 +462,10 @@ int envelope_enqueue(const float* in, int64_t n_rows, int n, float* env, float* 
   for (int k = 0; k < P.n_stages; ++k) primes = primes || (P.radix[k] > 5 && P.radix[k] != 8);
   const dim3 grid = dim3(static_cast<unsigned>(blocks)), block = dim3(kEnvThreads);
   switch (n) {
-    case 2048: hipLaunchKernelGGL((envelope_kernel<2048, false>), grid, block, lds, s, in, n_rows, P, env, row_max); break;
-    case 1024: hipLaunchKernelGGL((envelope_kernel<1024, false>), grid, block, lds, s, in, n_rows, P, env, row_max); break;
-    case 512: hipLaunchKernelGGL((envelope_kernel<512, false>), grid, block, lds, s, in, n_rows, P, env, row_max); break;
-    case 256: hipLaunchKernelGGL((envelope_kernel<256, false>), grid, block, lds, s, in, n_rows, P, env, row_max); break;
+    case 2048: hipLaunchKernelGGL((envelope_pow2_kernel<2048>), grid, block, lds, s, in, n_rows, env, row_max); break;
+    case 1024: hipLaunchKernelGGL((envelope_pow2_kernel<1024>), grid, block, lds, s, in, n_rows, env, row_max); break;
+    case 512: hipLaunchKernelGGL((envelope_pow2_kernel<512>), grid, block, lds, s, in, n_rows, env, row_max); break;
+    case 256: hipLaunchKernelGGL((envelope_pow2_kernel<256>), grid, block, lds, s, in, n_rows, env, row_max); break;
     default:
       if (primes)
         hipLaunchKernelGGL((envelope_kernel<0, true>), grid, block, lds, s, in, n_rows, P, env, row_max);

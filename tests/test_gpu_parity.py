@@ -174,7 +174,7 @@ def test_beamform_deterministic(usbf):
 
 # ------------------------------------------------------------------ envelope, log, scan
 
-@pytest.mark.parametrize("n", [8, 60, 1000, 1024, 1536, 2048, 1408, 1664, 1792, 950, 850, 1922])
+@pytest.mark.parametrize("n", [8, 60, 256, 512, 1000, 1024, 1536, 2048, 1408, 1664, 1792, 950, 850, 1922])
 def test_envelope_matches_oracle(usbf, n):
     rng = np.random.default_rng(n)
     x = rng.standard_normal((37, n)).astype(np.float32)
