@@ -13,7 +13,10 @@
  * grows with depth (aperture width depth / F#, Hann or rectangular), summed over
  * elements and normalised by the sum of weights.  T_tx is the time a focused
  * transmit wave needs to reach p, modelled as a wave converging on (and diverging
- * from) a virtual source at the focus.  Everything here is float64 except the
+ * from) a virtual source at the focus; an infinite focus is a plane wave, whose
+ * wavefront passes the transmit origin at t = 0 (c T_tx = (p - o_t).u_t; plane-wave
+ * imaging is among the protocols the paper intends to add, Sec. 2).  Everything here is
+ * float64 except the
  * integer decisions (sample index, aperture membership, record bounds), which are
  * taken by tof32() below in binary32 exactly as the GPU library takes them.
  *
@@ -112,6 +115,7 @@ static float dtx32(const line32_t* L, float r) {
     l2 = l2 + w1 * w1;
     l2 = l2 + w2 * w2;
   }
+  if (isinf(L->F)) return amr; /* plane wave: c T_tx - r is the projection part alone */
   float amF = amr + (r - L->F);
   float pf = sqrtf(amF * amF + l2);
   float den = pf + fabsf(amF);
@@ -203,7 +207,7 @@ static void line64_setup(const og_t* G, int l, line64_t* L) {
   unit3d(G->line_dir + 3 * l, L->u);
   unit3d(G->tx_dir + 3 * t, L->ut);
   L->F = G->tx_focus[t];
-  for (int i = 0; i < 3; ++i) L->f[i] = L->ot[i] + L->F * L->ut[i];
+  for (int i = 0; i < 3; ++i) L->f[i] = isinf(L->F) ? 0.0 : L->ot[i] + L->F * L->ut[i];
 }
 
 static double dist3(const double* a, const double* b) {
@@ -220,6 +224,10 @@ static double depth64(const og_t* G, int j) {
 static void pixel64(const line64_t* L, double r, double* p, double* ctx) {
   for (int i = 0; i < 3; ++i) p[i] = L->o[i] + r * L->u[i];
   double a = (p[0] - L->ot[0]) * L->ut[0] + (p[1] - L->ot[1]) * L->ut[1] + (p[2] - L->ot[2]) * L->ut[2];
+  if (isinf(L->F)) { /* plane wave: the wavefront passes the transmit origin at t = 0 */
+    *ctx = a;
+    return;
+  }
   double pf = dist3(p, L->f);
   *ctx = (a >= L->F) ? L->F + pf : L->F - pf;
 }

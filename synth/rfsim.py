@@ -4,7 +4,8 @@ Forward model: every scatterer k with amplitude a_k echoes a 2-cycle
 Gaussian-windowed pulse g(t) = cos(2 pi f0 t) exp(-t^2 / 2 s^2) (envelope FWHM of two
 periods, cut at |t| <= 3 s) that reaches element e of transmit t after the focused-wave
 travel time: the wave converges on a virtual source at the focus, so the transmit
-time is (F +- |p - focus|)/c, plus the receive path |e - p|/c.  White Gaussian noise at
+time is (F +- |p - focus|)/c (a plane wave, infinite focus: (p - o).u / c), plus the
+receive path |e - p|/c.  White Gaussian noise at
 a stated SNR is added and the frame is quantised to int16 (peak 30000).
 
 Implementation: arrivals are deposited on a grid 16x finer than the sampling grid
@@ -48,10 +49,14 @@ def arrival_samples(g: Geometry, tx: int, pos: torch.Tensor, el: torch.Tensor) -
     o = torch.tensor(g.tx_origin[tx], dtype=torch.float64, device=dev)
     d = torch.tensor(_unit(g.tx_dir[tx]), dtype=torch.float64, device=dev)
     F = float(g.tx_focus[tx])
-    focus = o + F * d
     axial = (pos - o) @ d
-    to_focus = torch.linalg.norm(pos - focus, dim=1)
-    t_tx = torch.where(axial >= F, F + to_focus, F - to_focus) / g.c
+    if np.isinf(F):
+        # plane wave: the wavefront passes the transmit origin at t = 0
+        t_tx = axial / g.c
+    else:
+        focus = o + F * d
+        to_focus = torch.linalg.norm(pos - focus, dim=1)
+        t_tx = torch.where(axial >= F, F + to_focus, F - to_focus) / g.c
     t_rx = torch.cdist(el, pos) / g.c          # [n_el, K]
     return (t_tx[None, :] + t_rx - g.t0) * g.fs
 
