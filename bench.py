@@ -106,6 +106,9 @@ WORKLOADS = {
                                      "64 x 1024 lines -> 256 x 256 B-mode"),
     "volume": ("config_volume_3d", 1, "matrix 32 x 32 el, 1024 steered tx/lines over +-30 deg, 2000 int16 samples "
                                       "@ 20 MHz, 32 x 32 x 1000 lines -> 128^3 B-mode volume"),
+    "planewave": ("config_planewave_2d", 16, "plane-wave imaging, linear 128 el, 11 steered plane waves (-10..10 deg), "
+                                             "256 lines x 2048 depths beamformed per wave, 4096 int16 samples @ 40 MHz, "
+                                             "coherent compounding -> 512 x 512 B-mode"),
     "stream": ("stream_mix", 100, "uneven stream of 100 items, seeded 70/30 mix of linear frames (64/128/192 el, "
                                   "2048..4096 samples, n_el/2 transmits x 4 lines, 512^2 images) and matrix volumes "
                                   "(16x16 or 32x32 el, 1000..2000 samples, 32x32 lines, 128^3 volumes), one "
@@ -134,6 +137,9 @@ def cpu_baseline(g, rf_host, budget_s):
     n = 0
     while n < rf_host.shape[0]:
         y = oracle.das(g, rf_host[n:n + 1])
+        n_angles = getattr(g, "n_angles", 0)
+        if n_angles:  # coherent compounding of the plane-wave lines
+            y = y.reshape(1, n_angles, g.n_lines // n_angles, g.n_depth).mean(axis=1)
         if g.scan.kind == 1:
             oracle.bmode_3d(y[0], g.scan, 50.0)
         else:
@@ -145,7 +151,8 @@ def cpu_baseline(g, rf_host, budget_s):
     pcs = n * g.n_lines * g.n_depth * g.n_el
     return {"value": pcs / dt, "unit": "pixel·channel samples/s", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": f"{n} frame(s) of the batch through the float64 oracle (DAS + envelope + log + scan "
+            "sample": f"{n} frame(s) of the batch through the float64 oracle (DAS"
+                      f"{' + compounding' if getattr(g, 'n_angles', 0) else ''} + envelope + log + scan "
                       f"conversion), {dt:.1f} s"}
 
 
@@ -196,11 +203,13 @@ def main():
     dg = u.DeviceGeometry(g, dev)
     ws = u.BmodeWorkspace(dg, F)
     lines = ws.lines(dg)
-    row_max = torch.empty((F, g.n_lines), dtype=torch.float32, device=dev)
+    n_angles = getattr(g, "n_angles", 0)
+    # plane waves: the lines of every angle are compounded into the image lines first
+    det = torch.empty((F, g.n_lines // n_angles, g.n_depth), dtype=torch.float32, device=dev) if n_angles else lines
+    row_max = torch.empty(det.shape[:2], dtype=torch.float32, device=dev)
     img = torch.empty((F, *dg.scan_shape), dtype=torch.float32, device=dev)
-    ls_ws = torch.empty(4096, dtype=torch.uint8, device=dev)
 
-    iq_env = torch.empty_like(lines) if args.envelope == "iq" else None
+    iq_env = torch.empty_like(det) if args.envelope == "iq" else None
     line_fs = float(g.fs) / g.depth_step
     iq_bands = [0.8 * g.f0, g.f0, 1.2 * g.f0]
 
@@ -210,13 +219,15 @@ def main():
         u.beamform(rf, dg, out=lines)
         if ev is not None:
             ev[1].record()
+        if n_angles:
+            u.compound(lines, n_angles, out=det)
         if iq_env is not None:
-            u.envelope_iq(lines, line_fs, iq_bands, 0.4 * g.f0, 63, out=iq_env, row_max=row_max)
+            u.envelope_iq(det, line_fs, iq_bands, 0.4 * g.f0, 63, out=iq_env, row_max=row_max)
         else:
-            u.envelope(lines, out=lines, row_max=row_max)
+            u.envelope(det, out=det, row_max=row_max)
         if ev is not None:
             ev[2].record()
-        u.log_scan_convert(iq_env if iq_env is not None else lines, dg, 50.0, row_max=row_max, out=img)
+        u.log_scan_convert(iq_env if iq_env is not None else det, dg, 50.0, row_max=row_max, out=img)
         if ev is not None:
             ev[3].record()
 
@@ -235,10 +246,13 @@ def main():
     scan_ms = np.array([e[2].elapsed_time(e[3]) for e in evs])
     step_ms = wall * 1e3 / args.steps
 
-    # the whole-pipeline entry point gives the same image
-    ref = u.bmode(rf, dg, 50.0, ws=u.BmodeWorkspace(dg, F))
-    torch.cuda.synchronize()
-    same = bool(torch.equal(ref, img)) if iq_env is None else None  # usbf_bmode uses the analytic-signal envelope
+    # the whole-pipeline entry point gives the same image (it has the analytic-signal envelope
+    # and no compounding)
+    same = None
+    if iq_env is None and not n_angles:
+        ref = u.bmode(rf, dg, 50.0, ws=u.BmodeWorkspace(dg, F))
+        torch.cuda.synchronize()
+        same = bool(torch.equal(ref, img))
 
     pcs = F * g.n_lines * g.n_depth * g.n_el
     rf_bytes = rf.numel() * 2
@@ -261,7 +275,8 @@ def main():
         "config": {"workload": desc, "frames_per_batch": F, "envelope": args.envelope,
                    "unique_frames": min(args.unique_frames, F), "dyn_range_db": 50},
         "frames_per_s": F / (step_ms * 1e-3),
-        "stage_ms": {"das": float(das_ms.mean()), "envelope": float(env_ms.mean()),
+        "stage_ms": {"das": float(das_ms.mean()),
+                     ("compound+envelope" if n_angles else "envelope"): float(env_ms.mean()),
                      "log_scan": float(scan_ms.mean())},
         "bmode_entry_matches": same,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

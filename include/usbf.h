@@ -50,9 +50,15 @@ extern "C" {
  * Probe, transmit and scanline geometry (device arrays).
  *   el_pos      [n_el][3]    element centres; the array lies in the plane z = 0.
  *   tx_origin   [n_tx][3]    transmit beam origin;  tx_dir [n_tx][3] its direction (any
- *                            length > 0, normalised inside);  tx_focus [n_tx] focal range > 0
- *                            along tx_dir.  The focused wave is modelled as converging on,
- *                            then diverging from, a virtual source at the focus.
+ *                            length > 0, normalised inside);  tx_focus [n_tx] signed focal
+ *                            range F along tx_dir.  The wave is modelled as converging on,
+ *                            then diverging from, a virtual source at tx_origin + F u, reached
+ *                            at t = F / c: F > 0 is a focused transmit; F < 0 a diverging wave
+ *                            from a source |F| behind the array; +infinity a plane wave, whose
+ *                            wavefront passes tx_origin at t = 0 (transmit time
+ *                            (p - tx_origin).u / c; plane-wave imaging, Sec. 2).  F = 0 is a
+ *                            spherical wave from tx_origin itself; NaN is not meaningful
+ *                            (not checked: the array is in device memory).
  *   line_origin [n_lines][3] scanline origin; line_dir [n_lines][3] its direction;
  *   line_tx     [n_lines]    transmit whose echoes form the line (multi-line acquisition
  *                            when several lines share one transmit, Sec. 2 method list item 1).
@@ -60,8 +66,9 @@ extern "C" {
  *               2: matrix array, separable aperture along x and y.
  *   lines_per_tx  work-grouping hint, no effect on results: G > 1 announces that each run of
  *               G consecutive lines starting at a multiple of G shares one transmit, so the
- *               channel data of that transmit is staged once for the G lines (G = 2, 4, 8 are
- *               used; 0 or 1: no grouping).  A wrong hint only costs speed.
+ *               channel data of that transmit is staged once for the lines of a tile (tiles of
+ *               8 lines for G = 8, of 4 for other multiples of 4, of 2 for other even G; 0 or
+ *               1: no grouping).  A wrong hint only costs speed.
  * The receive aperture is centred on the line origin.
  */
 typedef struct usbf_geometry {
@@ -169,6 +176,16 @@ int usbf_envelope(const float* in, int64_t n_rows, int32_t n, float* env, float*
  */
 int usbf_envelope_iq(const float* in, int64_t n_rows, int32_t n, float fs, const float* freqs, int32_t n_bands,
                      float bandwidth, int32_t n_taps, float* env, float* row_max, hipStream_t stream);
+
+/*
+ * Coherent compounding (plane-wave imaging, Sec. 2: every line is beamformed once per steered
+ * plane wave and the results are averaged before detection):
+ *   out[f][i] = (1 / n_groups) sum_g in[f][g][i],  summed in group order.
+ *   in   float [n_frames][n_groups][group_len] device;  out float [n_frames][group_len] device,
+ *        not overlapping in.  1 <= n_frames <= 65535.
+ */
+int usbf_compound(const float* in, int32_t n_frames, int32_t n_groups, int64_t group_len, float* out,
+                  hipStream_t stream);
 
 /*
  * Log compression to a display range (Sec. 1 pipeline list; Sec. 2 method list item 4):

@@ -60,6 +60,7 @@ _SIGS = {
     "usbf_beamform": (I32, [P, I32, P, P, P, P]),
     "usbf_envelope": (I32, [P, I64, I32, P, P, P]),
     "usbf_envelope_iq": (I32, [P, I64, I32, F32, P, I32, F32, I32, P, P, P]),
+    "usbf_compound": (I32, [P, I32, I32, I64, P, P]),
     "usbf_log_compress": (I32, [P, I32, I64, F32, F32, P, P, ctypes.c_size_t, P]),
     "usbf_scan_convert": (I32, [P, I32, P, P, P]),
     "usbf_log_scan_convert": (I32, [P, P, I32, P, F32, F32, P, P, ctypes.c_size_t, P]),
@@ -134,8 +135,15 @@ def _need_cuda(t: torch.Tensor, name: str, dtype=None):
 
 
 def lines_per_tx_hint(line_tx) -> int:
-    """Largest G in (8, 4, 2) such that every run of G consecutive lines shares a transmit."""
+    """Length of the runs of consecutive lines that share a transmit when all runs have the same
+    length; else the largest G in (8, 4, 2) such that every run of G consecutive lines shares a
+    transmit; else 1."""
     lt = np.asarray(line_tx)
+    if lt.size:
+        change = np.flatnonzero(lt[1:] != lt[:-1])
+        run = int(change[0]) + 1 if change.size else int(lt.size)
+        if lt.size % run == 0 and np.all(lt.reshape(-1, run) == lt.reshape(-1, run)[:, :1]):
+            return run
     for G in (8, 4, 2):
         n = (lt.size // G) * G
         if n and np.all(lt[:n].reshape(-1, G) == lt[:n].reshape(-1, G)[:, :1]):
@@ -236,6 +244,20 @@ def envelope_iq(x: torch.Tensor, fs: float, freqs, bandwidth: float, n_taps: int
     _check(lib().usbf_envelope_iq(_ptr(x), rows, n, float(fs), f, len(freqs), float(bandwidth), int(n_taps),
                                   _ptr(out), _ptr(rm), _stream(x.device)))
     return (out, rm) if rm is not None else out
+
+
+def compound(x: torch.Tensor, n_groups: int, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Coherent compounding: x [F, n_groups * L, ...] (per-transmit beamformed lines, transmit
+    major) -> mean over the transmits, [F, L, ...]."""
+    _need_cuda(x, "x", torch.float32)
+    F = x.shape[0]
+    per = x.numel() // F
+    if per % n_groups:
+        raise ValueError("lines are not a multiple of n_groups")
+    if out is None:
+        out = torch.empty((F, x.shape[1] // n_groups, *x.shape[2:]), dtype=torch.float32, device=x.device)
+    _check(lib().usbf_compound(_ptr(x), F, n_groups, per // n_groups, _ptr(out), _stream(x.device)))
+    return out
 
 
 def log_compress(env: torch.Tensor, dyn_range_db: float = 50.0, ref: float | None = None,

@@ -744,13 +744,14 @@ int launch_persistent(const BatchItemDev* d_items, int n_items, int total_units,
   return check_launch("das_persistent_kernel");
 }
 
+// Lines per tile: the lines of a transmit come in runs of lines_per_tx (a hint; any mapping is
+// beamformed correctly), so tiles of 8, 4 or 2 lines share their staged channel data.
 int beamform_enqueue(const int16_t* rf, int32_t n_frames, const DasArgs& a, float* out, hipStream_t s) {
-  switch (a.lines_per_tx) {
-    case 2: return launch_das_g<2>(rf, n_frames, a, out, s);
-    case 4: return launch_das_g<4>(rf, n_frames, a, out, s);
-    case 8: return launch_das_g<8>(rf, n_frames, a, out, s);
-    default: return launch_das_g<1>(rf, n_frames, a, out, s);
-  }
+  const int lpt = a.lines_per_tx;
+  if (lpt == 8) return launch_das_g<8>(rf, n_frames, a, out, s);
+  if (lpt >= 4 && lpt % 4 == 0) return launch_das_g<4>(rf, n_frames, a, out, s);
+  if (lpt >= 2 && lpt % 2 == 0) return launch_das_g<2>(rf, n_frames, a, out, s);
+  return launch_das_g<1>(rf, n_frames, a, out, s);
 }
 
 }  // namespace usbf

@@ -91,6 +91,7 @@ __device__ inline float small_tx_delay(const LineGeom& L, float r) {
     l2 = l2 + w1 * w1;
     l2 = l2 + w2 * w2;
   }
+  if (isinf(L.F)) return amr;  // plane wave (infinite focus): the projection part alone
   float m = amr + (r - L.F);
   float den = sqrtf(m * m + l2) + fabsf(m);
   if (den > 0.0f) return amr + (m >= 0.0f ? l2 : -l2) / den;

@@ -259,12 +259,14 @@ def stream_mix(seed: int = 0, n_items: int = 100, frac_2d: float = 0.7) -> list:
 
 
 def config_planewave_2d(n_el: int = 128, n_angles: int = 11, max_angle_deg: float = 10.0, n_samples: int = 4096,
-                        lines: int = 256, scan_n=(512, 512)) -> Geometry:
+                        lines: int = 256, scan_n=(512, 512), focus: float = np.inf) -> Geometry:
     """Plane-wave imaging with the linear array: n_angles plane waves steered over
     +-max_angle_deg from the array centre (infinite focus); every one of the `lines` receive
     lines (half the element pitch apart) is beamformed for every angle, so the geometry holds
     n_angles x lines lines, angle-major (line a * lines + l belongs to transmit a); the scan
-    grid is that of the `lines` compounded lines."""
+    grid is that of the `lines` compounded lines.  A negative `focus` gives diverging waves
+    instead: each transmit spreads from a virtual source |focus| behind the array centre,
+    along the steering direction."""
     el = linear_array(n_el, 0.3e-3)
     lx = (np.arange(lines, dtype=np.float64) - (lines - 1) / 2.0) * 0.15e-3
     theta = np.radians(np.linspace(-max_angle_deg, max_angle_deg, n_angles))
@@ -273,11 +275,12 @@ def config_planewave_2d(n_el: int = 128, n_angles: int = 11, max_angle_deg: floa
     line_tx = np.ascontiguousarray(np.repeat(np.arange(n_angles, dtype=np.int32), lines))
     tx_origin = _f32(np.zeros((n_angles, 3)))
     tx_dir = _f32(np.stack([np.sin(theta), np.zeros(n_angles), np.cos(theta)], axis=1))
-    tx_focus = np.full(n_angles, np.inf, dtype=np.float32)
+    tx_focus = np.full(n_angles, focus, dtype=np.float32)
     depth_step = 2
     n_depth = n_samples // depth_step
     c, fs = 1540.0, 40e6
-    g = Geometry(name=f"planewave{n_el}_{n_angles}angles_{n_samples}", el_pos=el, tx_origin=tx_origin,
+    kind = "planewave" if np.isinf(focus) else "divergingwave"
+    g = Geometry(name=f"{kind}{n_el}_{n_angles}angles_{n_samples}", el_pos=el, tx_origin=tx_origin,
                  tx_dir=tx_dir, tx_focus=tx_focus, line_origin=line_origin, line_dir=line_dir, line_tx=line_tx,
                  array_dims=1, c=float(np.float32(c)), fs=float(np.float32(fs)), t0=0.0, n_samples=n_samples,
                  depth_start=0, depth_step=depth_step, n_depth=n_depth, f_number=1.0, window=HANN, f0=5e6)

@@ -188,3 +188,11 @@ def test_envelope_iq_rejects(u):
     assert L.usbf_envelope_iq(FAKE, 4, 2048, 40e6, f, 3, 0.0, 63, FAKE + 64, None, None) == -1
     bad = (ctypes.c_float * 3)(5e6, 25e6, 6e6)
     assert L.usbf_envelope_iq(FAKE, 4, 2048, 40e6, bad, 3, 2e6, 63, FAKE + 64, None, None) == -1
+
+
+def test_compound_rejects(u):
+    L = u.lib()
+    assert L.usbf_compound(None, 1, 2, 100, FAKE, None) == -1
+    assert L.usbf_compound(FAKE, 0, 2, 100, FAKE + 4096, None) == -1
+    assert L.usbf_compound(FAKE, 1, 0, 100, FAKE + 4096, None) == -1
+    assert L.usbf_compound(FAKE, 1, 2, 100, FAKE + 400, None) == -1   # out inside the input
