@@ -169,6 +169,9 @@ def main():
     ap.add_argument("--envelope", default="hilbert", choices=["hilbert", "iq"],
                     help="envelope detector: analytic signal (default) or IQ demodulation with three "
                          "compounded bands at 0.8, 1.0, 1.2 f0 (63 taps, bandwidth 0.4 f0)")
+    ap.add_argument("--apod-sets", type=int, default=1, choices=[1, 2, 4],
+                    help="beamform with this many apodization sets in one pass (f-number 1.0 Hann, "
+                         "1.75 rect, 1.5 Hann, 2.5 rect) and take every set through the pipeline")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the timed steps, copy a 1 GiB buffer (the reference kernel for HBM counters)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -201,13 +204,17 @@ def main():
     torch.cuda.synchronize()
     log(f"inputs: {tuple(rf.shape)} int16 ({rf.numel() * 2 / 2**30:.2f} GiB) generated in {time.perf_counter() - t:.1f} s")
     dg = u.DeviceGeometry(g, dev)
-    ws = u.BmodeWorkspace(dg, F)
+    n_sets = args.apod_sets
+    set_fn, set_win = [1.0, 1.75, 1.5, 2.5][:n_sets], [1, 0, 1, 0][:n_sets]
+    # with several apodization sets every set is an image of its own: S x F images per step
+    FI = F * n_sets
+    ws = u.BmodeWorkspace(dg, FI)
     lines = ws.lines(dg)
     n_angles = getattr(g, "n_angles", 0)
     # plane waves: the lines of every angle are compounded into the image lines first
-    det = torch.empty((F, g.n_lines // n_angles, g.n_depth), dtype=torch.float32, device=dev) if n_angles else lines
+    det = torch.empty((FI, g.n_lines // n_angles, g.n_depth), dtype=torch.float32, device=dev) if n_angles else lines
     row_max = torch.empty(det.shape[:2], dtype=torch.float32, device=dev)
-    img = torch.empty((F, *dg.scan_shape), dtype=torch.float32, device=dev)
+    img = torch.empty((FI, *dg.scan_shape), dtype=torch.float32, device=dev)
 
     iq_env = torch.empty_like(det) if args.envelope == "iq" else None
     line_fs = float(g.fs) / g.depth_step
@@ -216,7 +223,10 @@ def main():
     def step(ev=None):
         if ev is not None:
             ev[0].record()
-        u.beamform(rf, dg, out=lines)
+        if n_sets > 1:
+            u.beamform_sets(rf, dg, set_fn, set_win, out=lines.view(n_sets, F, *lines.shape[1:]))
+        else:
+            u.beamform(rf, dg, out=lines)
         if ev is not None:
             ev[1].record()
         if n_angles:
@@ -249,14 +259,14 @@ def main():
     # the whole-pipeline entry point gives the same image (it has the analytic-signal envelope
     # and no compounding)
     same = None
-    if iq_env is None and not n_angles:
+    if iq_env is None and not n_angles and n_sets == 1:
         ref = u.bmode(rf, dg, 50.0, ws=u.BmodeWorkspace(dg, F))
         torch.cuda.synchronize()
         same = bool(torch.equal(ref, img))
 
-    pcs = F * g.n_lines * g.n_depth * g.n_el
+    pcs = FI * g.n_lines * g.n_depth * g.n_el
     rf_bytes = rf.numel() * 2
-    out_bytes = F * g.n_lines * g.n_depth * 4
+    out_bytes = FI * g.n_lines * g.n_depth * 4
     das_s = float(das_ms.mean()) * 1e-3
     achieved = (rf_bytes + out_bytes) / das_s / 1e9
     result = {
@@ -272,16 +282,16 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": desc, "frames_per_batch": F, "envelope": args.envelope,
+        "config": {"workload": desc, "frames_per_batch": F, "envelope": args.envelope, "apod_sets": n_sets,
                    "unique_frames": min(args.unique_frames, F), "dyn_range_db": 50},
-        "frames_per_s": F / (step_ms * 1e-3),
+        "frames_per_s": FI / (step_ms * 1e-3),
         "stage_ms": {"das": float(das_ms.mean()),
                      ("compound+envelope" if n_angles else "envelope"): float(env_ms.mean()),
                      "log_scan": float(scan_ms.mean())},
         "bmode_entry_matches": same,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic_from_profile("das", F), "kernel": "das (delay-and-sum)",
+                     "traffic": traffic_from_profile("das", F) if n_sets == 1 else None, "kernel": "das (delay-and-sum)",
                      "algorithmic_bytes": rf_bytes + out_bytes},
     }
     if args.calib_copy:

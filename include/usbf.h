@@ -150,6 +150,24 @@ int usbf_beamform(const int16_t* rf, int32_t n_frames, const usbf_geometry* geom
                   const usbf_rx* rx, float* out, hipStream_t stream);
 
 /*
+ * Several differently parameterised delay-and-sum beamformers over the same channel data in
+ * one pass (Sec. 2: two differently parametrised beamforming runs on the same input): set k
+ * has its own f-number f_numbers[k] and window windows[k] (USBF_WINDOW_*), everything else
+ * (geometry, depth grid, c, fs, t0) is shared.  Set k's result equals usbf_beamform() with
+ * rx->f_number = f_numbers[k] and rx->window = windows[k] (the same binary32 rule and the
+ * same summation order); the channel data is staged once for all sets, so the pass costs
+ * far less than n_sets separate calls.  rx->f_number and rx->window must still be valid
+ * and are otherwise unused.
+ *   rf         int16 [n_frames][n_tx][n_el][n_samples] (device)
+ *   f_numbers  float [n_sets], windows int32 [n_sets] (host; read during the call)
+ *   out        float [n_sets][n_frames][n_lines][n_depth] (device)
+ * n_sets = 1, 2 or 4; other limits as usbf_beamform().
+ */
+int usbf_beamform_sets(const int16_t* rf, int32_t n_frames, const usbf_geometry* geom,
+                       const usbf_rx* rx, int32_t n_sets, const float* f_numbers,
+                       const int32_t* windows, float* out, hipStream_t stream);
+
+/*
  * Envelope detection (Sec. 1 pipeline list, "envelope detection"; the Hilbert-transform
  * envelope of the PSF study, Sec. 3.2): for each of n_rows rows of length n,
  *   env = | IDFT( H . DFT(in) ) |,  H[0] = 1, H[k] = 2 for 0 < k < n/2, H[n/2] = 1 (n even),

@@ -58,6 +58,7 @@ class CBatchShape(ctypes.Structure):
 # name -> (restype, argtypes)
 _SIGS = {
     "usbf_beamform": (I32, [P, I32, P, P, P, P]),
+    "usbf_beamform_sets": (I32, [P, I32, P, P, I32, P, P, P, P]),
     "usbf_envelope": (I32, [P, I64, I32, P, P, P]),
     "usbf_envelope_iq": (I32, [P, I64, I32, F32, P, I32, F32, I32, P, P, P]),
     "usbf_compound": (I32, [P, I32, I32, I64, P, P]),
@@ -205,6 +206,27 @@ def beamform(rf: torch.Tensor, dg: DeviceGeometry, out: torch.Tensor | None = No
     if out is None:
         out = torch.empty((F, dg.n_lines, dg.n_depth), dtype=torch.float32, device=rf.device)
     _check(lib().usbf_beamform(_ptr(rf), F, ctypes.byref(dg.geom), ctypes.byref(dg.rx), _ptr(out), _stream(rf.device)))
+    return out
+
+
+def beamform_sets(rf: torch.Tensor, dg: DeviceGeometry, f_numbers, windows, out: torch.Tensor | None = None):
+    """Delay-and-sum with several apodizations (f-number, window) in one pass over the channel
+    data.  rf int16 [F, n_tx, n_el, S] -> float32 [n_sets, F, n_lines, n_depth]."""
+    _need_cuda(rf, "rf", torch.int16)
+    if rf.dim() == 3:
+        rf = rf.unsqueeze(0)
+    F = rf.shape[0]
+    if tuple(rf.shape[1:]) != (dg.n_tx, dg.n_el, dg.n_samples):
+        raise ValueError(f"rf shape {tuple(rf.shape)} does not match geometry")
+    n = len(f_numbers)
+    if len(windows) != n:
+        raise ValueError("one window per f-number")
+    fn = (ctypes.c_float * n)(*[float(v) for v in f_numbers])
+    wn = (ctypes.c_int32 * n)(*[int(v) for v in windows])
+    if out is None:
+        out = torch.empty((n, F, dg.n_lines, dg.n_depth), dtype=torch.float32, device=rf.device)
+    _check(lib().usbf_beamform_sets(_ptr(rf), F, ctypes.byref(dg.geom), ctypes.byref(dg.rx), n, fn, wn, _ptr(out),
+                                    _stream(rf.device)))
     return out
 
 

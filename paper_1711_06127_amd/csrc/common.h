@@ -41,6 +41,8 @@ __device__ inline uint32_t xcd_swizzle(uint32_t bid, uint32_t nblocks) {
 
 // Geometry in kernel-argument form (device pointers, sizes) plus the binary32 constants of
 // the delay rule, computed once on the host with the same IEEE operations the rule names.
+constexpr int kMaxSets = 4;
+
 struct DasArgs {
   const float* el_pos;
   const float* tx_origin;
@@ -53,6 +55,13 @@ struct DasArgs {
   int32_t n_samples, depth_start, depth_step, n_depth;
   float h, K, T0, F2, f_number;
   int32_t window;
+  // apodization parameter sets beamformed together from one staging of the channel data: tile
+  // slot s / (G / n_sets) uses set s; set 0 is (f_number, window) above.  Output of set s
+  // starts set_stride floats after that of set 0.
+  int32_t n_sets;
+  float set_F2[kMaxSets], set_fn[kMaxSets];
+  int32_t set_window[kMaxSets];
+  int64_t set_stride;
 };
 
 int make_das_args(const usbf_geometry* g, const usbf_rx* rx, DasArgs* a);

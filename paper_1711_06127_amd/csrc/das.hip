@@ -137,6 +137,14 @@ __device__ inline int32_t rule_tap(const DasArgs& a, const LineGeom& L, const fl
   return fast_tap(a, b, small_tx_delay(L, r), E.x, E.y, r, r + r, r * r).i0;
 }
 
+// apodization set s of a tile slot (selects: an indexed read of the kernel-argument arrays would
+// go through scratch memory)
+__device__ inline void set_params(const DasArgs& a, int s, LineGeom& L) {
+  L.F2 = s == 0 ? a.set_F2[0] : s == 1 ? a.set_F2[1] : s == 2 ? a.set_F2[2] : a.set_F2[3];
+  L.fn = s == 0 ? a.set_fn[0] : s == 1 ? a.set_fn[1] : s == 2 ? a.set_fn[2] : a.set_fn[3];
+  L.window = s == 0 ? a.set_window[0] : s == 1 ? a.set_window[1] : s == 2 ? a.set_window[2] : a.set_window[3];
+}
+
 __device__ inline float lo16(uint32_t d) { return float(int16_t(d & 0xffffu)); }
 __device__ inline float hi16(uint32_t d) { return float(int16_t(d >> 16)); }
 
@@ -278,9 +286,12 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
   const TileLds<G, FS> t = carve<G, FS>(lds_raw, a.n_el);
 
   const int tid = threadIdx.x;
+  // slot g of the tile: line l0 + g % gl with apodization set g / gl (gl = G with one set)
   const int g = tid / TD;
-  const int l0 = group * G;
-  const int l = l0 + g;
+  const int gl = G / a.n_sets;
+  const int l0 = group * gl;
+  const int l = l0 + g % gl;
+  const int set = g / gl;
   const int j = dt * TD + tid % TD;
   const int j_first = dt * TD;
   const int j_last = min(a.n_depth, j_first + TD) - 1;
@@ -292,7 +303,10 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
 
   // ---- prologue: line constants, per-(line, element) receive constants, tap windows
   constexpr int ZERO = SH::BUFV;  // index of a buffer's zero vector
-  if (tid < G) line_geom(a, min(l0 + tid, a.n_lines - 1), t.lines[tid]);
+  if (tid < G) {
+    line_geom(a, min(l0 + tid % gl, a.n_lines - 1), t.lines[tid]);
+    set_params(a, tid / gl, t.lines[tid]);
+  }
   if (tid == 0) {
     V z;
 #pragma unroll
@@ -314,8 +328,8 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
       const ElemGeom E = elem_geom(a, Lg, e);
       const float2 E2 = make_float2(E.A, E.B);
       t.geo[gg * a.n_el + e] = E2;
-      if (l0 + gg >= a.n_lines || Lg.tx < 0) continue;
-      if (!in_aperture(a, E, r_last)) continue;
+      if (l0 + gg % gl >= a.n_lines || Lg.tx < 0) continue;
+      if (!in_aperture(Lg.F2, a.array_dims, E, r_last)) continue;
       const int shift = 8 * (e & 3);
       if (Lg.tx != t_grp) {
         atomicOr(&t.flg[e >> 2], 1 << shift);
@@ -352,7 +366,7 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
   const float r2 = r + r;
   const float rr = r * r;
   const float dtx = small_tx_delay(L, r);
-  const float inv_w = r > 0.0f ? a.f_number / r : 0.0f;
+  const float inv_w = r > 0.0f ? L.fn / r : 0.0f;
   const size_t tx_block = size_t(a.n_el) * S;              // samples per transmit
   const size_t frame_stride = size_t(a.n_tx) * tx_block;   // samples per frame
   const int16_t* grp_block = rf + size_t(t_grp < 0 ? 0 : t_grp) * tx_block;
@@ -406,9 +420,9 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
       const float2 E2 = geo[e];
       const float2 xy = t.exy[e];
       const ElemGeom E{E2.x, E2.y, xy.x - L.olx, xy.y - L.oly};
-      const bool act = lane_ok && e0 + k < a.n_el && in_aperture(a, E, r);
+      const bool act = lane_ok && e0 + k < a.n_el && in_aperture(L.F2, a.array_dims, E, r);
       if (!__any(act)) continue;  // no lane of the wave needs this element
-      const float w = act ? apod_weight(a.window, a.array_dims, E.dx, E.dy, inv_w) : 0.0f;
+      const float w = act ? apod_weight(L.window, a.array_dims, E.dx, E.dy, inv_w) : 0.0f;
       den += w;
       const Tap tp = fast_tap(a, b, dtx, E.A, E.B, r, r2, rr);
       const bool ok = act && tp.i0 >= 0 && tp.i0 <= S - 2;
@@ -549,7 +563,7 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
     }
     if (pix_ok) {
       const float inv = den > 0.0f ? 1.0f / den : 0.0f;
-      float* o = out + size_t(l) * a.n_depth + j;
+      float* o = out + size_t(set) * size_t(a.set_stride) + size_t(l) * a.n_depth + j;
       const size_t frame_out = size_t(a.n_lines) * a.n_depth;
 #pragma unroll
       for (int f = 0; f < FB; ++f) o[size_t(fb + f) * frame_out] = acc[f] * inv;
@@ -652,7 +666,8 @@ static int launch_das(const int16_t* rf, int frame0, int n_blocks, const DasArgs
   }
   ta.pshift = (a.depth_step % 2 == 0) ? 1 : 0;
   ta.n_dtiles = (a.n_depth + SH::TD - 1) / SH::TD;
-  const int64_t blocks = int64_t((a.n_lines + G - 1) / G) * ta.n_dtiles;
+  const int gl = G / a.n_sets;  // lines per tile
+  const int64_t blocks = int64_t((a.n_lines + gl - 1) / gl) * ta.n_dtiles;
   if (blocks > 0x7fffffff) return fail(USBF_EUNSUPPORTED, "too many tiles");
   const size_t lds = tile_lds_bytes<G, FS>(a.n_el);
   if (lds > size_t(kMaxTileLds))
@@ -745,13 +760,19 @@ int launch_persistent(const BatchItemDev* d_items, int n_items, int total_units,
 }
 
 // Lines per tile: the lines of a transmit come in runs of lines_per_tx (a hint; any mapping is
-// beamformed correctly), so tiles of 8, 4 or 2 lines share their staged channel data.
+// beamformed correctly), so tiles of 8, 4 or 2 lines share their staged channel data.  With
+// several apodization sets every line takes one slot per set: a tile holds G / n_sets lines
+// (G <= 8 slots), and all sets of those lines are summed from the same staged windows.
 int beamform_enqueue(const int16_t* rf, int32_t n_frames, const DasArgs& a, float* out, hipStream_t s) {
   const int lpt = a.lines_per_tx;
-  if (lpt == 8) return launch_das_g<8>(rf, n_frames, a, out, s);
-  if (lpt >= 4 && lpt % 4 == 0) return launch_das_g<4>(rf, n_frames, a, out, s);
-  if (lpt >= 2 && lpt % 2 == 0) return launch_das_g<2>(rf, n_frames, a, out, s);
-  return launch_das_g<1>(rf, n_frames, a, out, s);
+  int gl = lpt == 8 ? 8 : (lpt >= 4 && lpt % 4 == 0) ? 4 : (lpt >= 2 && lpt % 2 == 0) ? 2 : 1;
+  while (gl > 1 && gl * a.n_sets > 8) gl >>= 1;
+  switch (gl * a.n_sets) {
+    case 8: return launch_das_g<8>(rf, n_frames, a, out, s);
+    case 4: return launch_das_g<4>(rf, n_frames, a, out, s);
+    case 2: return launch_das_g<2>(rf, n_frames, a, out, s);
+    default: return launch_das_g<1>(rf, n_frames, a, out, s);
+  }
 }
 
 }  // namespace usbf
@@ -765,6 +786,30 @@ extern "C" int usbf_beamform(const int16_t* rf, int32_t n_frames, const usbf_geo
   if (st) return st;
   USBF_REQUIRE(rf && out, USBF_EINVAL, "null rf or out");
   USBF_REQUIRE(n_frames >= 1 && n_frames <= USBF_MAX_FRAMES, USBF_EINVAL, "n_frames %d out of range", n_frames);
+  return beamform_enqueue(rf, n_frames, a, out, stream);
+}
+
+extern "C" int usbf_beamform_sets(const int16_t* rf, int32_t n_frames, const usbf_geometry* geom, const usbf_rx* rx,
+                                  int32_t n_sets, const float* f_numbers, const int32_t* windows, float* out,
+                                  hipStream_t stream) {
+  DasArgs a;
+  int st = make_das_args(geom, rx, &a);
+  if (st) return st;
+  USBF_REQUIRE(rf && out && f_numbers && windows, USBF_EINVAL, "null rf, out, f_numbers or windows");
+  USBF_REQUIRE(n_frames >= 1 && n_frames <= USBF_MAX_FRAMES, USBF_EINVAL, "n_frames %d out of range", n_frames);
+  USBF_REQUIRE(n_sets == 1 || n_sets == 2 || n_sets == 4, USBF_EUNSUPPORTED, "n_sets must be 1, 2 or 4 (got %d)",
+               n_sets);
+  for (int k = 0; k < n_sets; ++k) {
+    USBF_REQUIRE(finite_pos(f_numbers[k]), USBF_EINVAL, "set %d: f_number must be finite and > 0", k);
+    USBF_REQUIRE(windows[k] == USBF_WINDOW_RECT || windows[k] == USBF_WINDOW_HANN, USBF_EINVAL,
+                 "set %d: unknown window", k);
+    volatile float fn = f_numbers[k];
+    a.set_F2[k] = fn + fn;  // the same binary32 operation as for a single set
+    a.set_fn[k] = fn;
+    a.set_window[k] = windows[k];
+  }
+  a.n_sets = n_sets;
+  a.set_stride = int64_t(n_frames) * a.n_lines * a.n_depth;
   return beamform_enqueue(rf, n_frames, a, out, stream);
 }
 

@@ -67,6 +67,13 @@ int make_das_args(const usbf_geometry* g, const usbf_rx* rx, DasArgs* a) {
   a->F2 = fn + fn;
   a->f_number = fn;
   a->window = rx->window;
+  a->n_sets = 1;
+  for (int k = 0; k < kMaxSets; ++k) {
+    a->set_F2[k] = a->F2;
+    a->set_fn[k] = fn;
+    a->set_window[k] = rx->window;
+  }
+  a->set_stride = 0;
   return USBF_OK;
 }
 

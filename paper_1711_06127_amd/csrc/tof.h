@@ -26,6 +26,8 @@ struct LineGeom {
   float F;                 // focal range of the line's transmit
   int same;                // line and transmit share origin and direction bit for bit
   int tx;                  // transmit index, -1 if out of range
+  float F2, fn;            // apodization: 2 f_number (aperture test) and f_number
+  int window;
 };
 
 __device__ inline float dot3(float ax, float ay, float az, float bx, float by, float bz) {
@@ -74,6 +76,9 @@ __device__ inline void line_geom(const DasArgs& a, int l, LineGeom& L) {
   L.Vy = L.uly - cl * uty;
   L.Vz = L.ulz - cl * utz;
   L.F = a.tx_focus[t];
+  L.F2 = a.F2;
+  L.fn = a.f_number;
+  L.window = a.window;
 }
 
 // c T_tx - r for depth r on the line.
@@ -170,10 +175,14 @@ __device__ inline Tap fast_tap(const DasArgs& a, int32_t b, float dtx, float A, 
   return delay_tap(a, b, dtx, small_rx_delay(A, B, r, r2, rr));
 }
 
-__device__ inline bool in_aperture(const DasArgs& a, const ElemGeom& E, float r) {
-  bool act = a.F2 * fabsf(E.dx) <= r;
-  if (a.array_dims == 2) act = act && (a.F2 * fabsf(E.dy) <= r);
+__device__ inline bool in_aperture(float F2, int array_dims, const ElemGeom& E, float r) {
+  bool act = F2 * fabsf(E.dx) <= r;
+  if (array_dims == 2) act = act && (F2 * fabsf(E.dy) <= r);
   return act;
+}
+
+__device__ inline bool in_aperture(const DasArgs& a, const ElemGeom& E, float r) {
+  return in_aperture(a.F2, a.array_dims, E, r);
 }
 
 #pragma clang fp contract(on)

@@ -82,6 +82,28 @@ def test_beamform_rejects_bad_geometry_and_sizes(u):
     assert L.usbf_beamform(FAKE, 1, ctypes.byref(g), ctypes.byref(r), FAKE, None) == -1
 
 
+def test_beamform_sets_rejects(u):
+    """Every call fails validation before anything is enqueued (FAKE pointers)."""
+    L = u.lib()
+    g, r = geom(u), rx(u)
+
+    def call(n, fns, wins, rf=FAKE, frames=1):
+        fa = (ctypes.c_float * max(1, len(fns)))(*fns) if fns is not None else None
+        wa = (ctypes.c_int32 * max(1, len(wins)))(*wins) if wins is not None else None
+        return L.usbf_beamform_sets(rf, frames, ctypes.byref(g), ctypes.byref(r), n, fa, wa, FAKE, None)
+
+    assert call(3, [1.0, 1.5, 2.0], [1, 1, 1]) == -3             # 1, 2 or 4 sets
+    assert call(8, [1.0] * 8, [1] * 8) == -3
+    assert call(0, [1.0], [1]) == -3
+    assert call(2, [1.0, 0.0], [1, 1]) == -1                     # f-number must be > 0
+    assert call(2, [1.0, float("inf")], [1, 1]) == -1
+    assert call(2, [1.0, 2.0], [1, 7]) == -1                     # unknown window
+    assert call(2, None, [1, 1]) == -1
+    assert call(2, [1.0, 2.0], None) == -1
+    assert call(2, [1.0, 2.0], [1, 1], rf=None) == -1
+    assert call(2, [1.0, 2.0], [1, 1], frames=0) == -1
+
+
 def test_envelope_and_log_reject(u):
     L = u.lib()
     assert L.usbf_envelope(FAKE, 4, 4, FAKE, None, None) == -3            # too short
