@@ -109,6 +109,10 @@ WORKLOADS = {
     "planewave": ("config_planewave_2d", 16, "plane-wave imaging, linear 128 el, 11 steered plane waves (-10..10 deg), "
                                              "256 lines x 2048 depths beamformed per wave, 4096 int16 samples @ 40 MHz, "
                                              "coherent compounding -> 512 x 512 B-mode"),
+    "overlap": ("config_overlap_2d", 16, "overlapping multi-line layout, linear 128 el, 128 focused tx, 255 lines "
+                                         "at half pitch (lines between two transmits interpolated from both beams: "
+                                         "382 beams of 2048 depths per frame), 4096 int16 samples @ 40 MHz -> "
+                                         "512 x 512 B-mode"),
     "stream": ("stream_mix", 100, "uneven stream of 100 items, seeded 70/30 mix of linear frames (64/128/192 el, "
                                   "2048..4096 samples, n_el/2 transmits x 4 lines, 512^2 images) and matrix volumes "
                                   "(16x16 or 32x32 el, 1000..2000 samples, 32x32 lines, 128^3 volumes), one "
@@ -130,6 +134,12 @@ def make_batch(g, n_frames, n_unique, device, volume=False):
     return torch.stack(frames)[idx].contiguous()
 
 
+def beams(g):
+    """Beamformed lines per frame that the image uses (unused line slots excluded)."""
+    import numpy as np
+    return int((np.asarray(g.line_tx) >= 0).sum())
+
+
 def cpu_baseline(g, rf_host, budget_s):
     """The oracle, as it stands, on a bounded sample of the same batch (whole frames)."""
     import oracle
@@ -140,6 +150,8 @@ def cpu_baseline(g, rf_host, budget_s):
         n_angles = getattr(g, "n_angles", 0)
         if n_angles:  # coherent compounding of the plane-wave lines
             y = y.reshape(1, n_angles, g.n_lines // n_angles, g.n_depth).mean(axis=1)
+        if hasattr(g, "combine_src"):  # overlapping lines: interpolation between transmits
+            y = oracle.combine_lines(y, g.combine_src, g.combine_w)
         if g.scan.kind == 1:
             oracle.bmode_3d(y[0], g.scan, 50.0)
         else:
@@ -148,11 +160,12 @@ def cpu_baseline(g, rf_host, budget_s):
         if time.perf_counter() - t0 >= budget_s:
             break
     dt = time.perf_counter() - t0
-    pcs = n * g.n_lines * g.n_depth * g.n_el
+    pcs = n * beams(g) * g.n_depth * g.n_el
     return {"value": pcs / dt, "unit": "pixel·channel samples/s", "cores": oracle.num_threads(),
             "kind": "oracle",
             "sample": f"{n} frame(s) of the batch through the float64 oracle (DAS"
-                      f"{' + compounding' if getattr(g, 'n_angles', 0) else ''} + envelope + log + scan "
+                      f"{' + compounding' if getattr(g, 'n_angles', 0) else ''}"
+                      f"{' + line interpolation' if hasattr(g, 'combine_src') else ''} + envelope + log + scan "
                       f"conversion), {dt:.1f} s"}
 
 
@@ -211,8 +224,17 @@ def main():
     ws = u.BmodeWorkspace(dg, FI)
     lines = ws.lines(dg)
     n_angles = getattr(g, "n_angles", 0)
-    # plane waves: the lines of every angle are compounded into the image lines first
-    det = torch.empty((FI, g.n_lines // n_angles, g.n_depth), dtype=torch.float32, device=dev) if n_angles else lines
+    overlap = hasattr(g, "combine_src")
+    # plane waves: the lines of every angle are compounded into the image lines first;
+    # overlapping layouts: the output lines are interpolated from the transmits' beams
+    if n_angles:
+        det = torch.empty((FI, g.n_lines // n_angles, g.n_depth), dtype=torch.float32, device=dev)
+    elif overlap:
+        det = torch.empty((FI, g.n_out_lines, g.n_depth), dtype=torch.float32, device=dev)
+        c_src = torch.as_tensor(g.combine_src, device=dev)
+        c_w = torch.as_tensor(g.combine_w, device=dev)
+    else:
+        det = lines
     row_max = torch.empty(det.shape[:2], dtype=torch.float32, device=dev)
     img = torch.empty((FI, *dg.scan_shape), dtype=torch.float32, device=dev)
 
@@ -231,6 +253,8 @@ def main():
             ev[1].record()
         if n_angles:
             u.compound(lines, n_angles, out=det)
+        elif overlap:
+            u.combine_lines(lines, c_src, c_w, out=det)
         if iq_env is not None:
             u.envelope_iq(det, line_fs, iq_bands, 0.4 * g.f0, 63, out=iq_env, row_max=row_max)
         else:
@@ -259,12 +283,12 @@ def main():
     # the whole-pipeline entry point gives the same image (it has the analytic-signal envelope
     # and no compounding)
     same = None
-    if iq_env is None and not n_angles and n_sets == 1:
+    if iq_env is None and not n_angles and not overlap and n_sets == 1:
         ref = u.bmode(rf, dg, 50.0, ws=u.BmodeWorkspace(dg, F))
         torch.cuda.synchronize()
         same = bool(torch.equal(ref, img))
 
-    pcs = FI * g.n_lines * g.n_depth * g.n_el
+    pcs = FI * beams(g) * g.n_depth * g.n_el
     rf_bytes = rf.numel() * 2
     out_bytes = FI * g.n_lines * g.n_depth * 4
     das_s = float(das_ms.mean()) * 1e-3
@@ -286,7 +310,8 @@ def main():
                    "unique_frames": min(args.unique_frames, F), "dyn_range_db": 50},
         "frames_per_s": FI / (step_ms * 1e-3),
         "stage_ms": {"das": float(das_ms.mean()),
-                     ("compound+envelope" if n_angles else "envelope"): float(env_ms.mean()),
+                     ("compound+envelope" if n_angles else "combine+envelope" if overlap else "envelope"):
+                         float(env_ms.mean()),
                      "log_scan": float(scan_ms.mean())},
         "bmode_entry_matches": same,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

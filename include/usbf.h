@@ -206,6 +206,22 @@ int usbf_compound(const float* in, int32_t n_frames, int32_t n_groups, int64_t g
                   hipStream_t stream);
 
 /*
+ * Weighted combination of beamformed lines (overlapping multi-line layouts: a line between
+ * two transmits is interpolated from both transmits' beams of it; Sec. 3.3, Table 1: 255 lines from 128
+ * transmits).  For every frame f, output line o and sample i:
+ *   out[f][o][i] = sum_k w[o][k] * in[f][src[o][k]][i]
+ * over the k = 0 .. k-1 whose source src[o][k] lies in [0, n_in) (others, e.g. -1, add
+ * nothing), accumulated in binary32 in k order.
+ *   in   float [n_frames][n_in][len]  (device);  out float [n_frames][n_out][len] (device),
+ *        not overlapping in
+ *   src  int32 [n_out][k], w float [n_out][k] (device)
+ * 1 <= n_frames, n_out <= 65535; 1 <= k <= 64.
+ */
+int usbf_combine_lines(const float* in, int32_t n_frames, int32_t n_in, int64_t len,
+                       const int32_t* src, const float* w, int32_t k, int32_t n_out,
+                       float* out, hipStream_t stream);
+
+/*
  * Log compression to a display range (Sec. 1 pipeline list; Sec. 2 method list item 4):
  *   out = clamp(1 + (20 / dyn_range_db) log10(env / ref), 0, 1),  out = 0 where env <= 0,
  * with ref the given reference, or when ref <= 0 the maximum of each frame.

@@ -149,6 +149,21 @@ def delay_gather(g, rf, pix):
     return out
 
 
+def combine_lines(y, src, w) -> np.ndarray:
+    """Output lines as weighted sums of beamformed lines, float64: out[..., m, :] =
+    sum_k w[m, k] y[..., src[m, k], :] over the sources that are lines of y (overlapping
+    multi-line layouts interpolate a line between two transmits from both beams of it,
+    Sec. 3.3, Table 1; coherent compounding is the case of equal weights)."""
+    y = np.asarray(y, np.float64)
+    n_in = y.shape[-2]
+    out = np.zeros(y.shape[:-2] + (len(src), y.shape[-1]))
+    for m in range(len(src)):
+        for s, wk in zip(src[m], w[m]):
+            if 0 <= int(s) < n_in:
+                out[..., m, :] += float(wk) * y[..., int(s), :]
+    return out
+
+
 # ---------------------------------------------------------------- envelope detection
 
 def analytic_filter(n: int) -> np.ndarray:

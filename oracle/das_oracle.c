@@ -299,6 +299,11 @@ void oracle_das(const og_t* G, const int16_t* rf, int32_t n_frames, int64_t n_pi
       l = (int)((q % per) / G->n_depth);
       j = (int)(q % G->n_depth);
     }
+    int t = G->line_tx[l];
+    if (t < 0 || t >= G->n_tx) { /* a line without a transmit is a line of zeros */
+      out[q] = 0.0;
+      continue;
+    }
     line32_t L32;
     line32_setup(G, l, &L32);
     line64_t L;
@@ -306,7 +311,6 @@ void oracle_das(const og_t* G, const int16_t* rf, int32_t n_frames, int64_t n_pi
     double r = depth64(G, j);
     double p[3], ctx;
     pixel64(&L, r, p, &ctx);
-    int t = G->line_tx[l];
     const int16_t* base = rf + (((int64_t)f * G->n_tx + t) * G->n_el) * S;
     double num = 0.0, den = 0.0;
     for (int e = 0; e < G->n_el; ++e) {
@@ -330,13 +334,17 @@ void oracle_delay_gather(const og_t* G, const int16_t* rf, int64_t n_pix, const 
   #pragma omp parallel for schedule(dynamic, 16)
   for (int64_t q = 0; q < n_pix; ++q) {
     int f = pix[3 * q], l = pix[3 * q + 1], j = pix[3 * q + 2];
+    int t = G->line_tx[l];
+    if (t < 0 || t >= G->n_tx) {
+      for (int e = 0; e < G->n_el; ++e) x[q * G->n_el + e] = 0.0;
+      continue;
+    }
     line32_t L32;
     line32_setup(G, l, &L32);
     line64_t L;
     line64_setup(G, l, &L);
     double p[3], ctx;
     pixel64(&L, depth64(G, j), p, &ctx);
-    int t = G->line_tx[l];
     const int16_t* base = rf + (((int64_t)f * G->n_tx + t) * G->n_el) * S;
     for (int e = 0; e < G->n_el; ++e) {
       tof32_t d;

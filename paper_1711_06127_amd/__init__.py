@@ -62,6 +62,7 @@ _SIGS = {
     "usbf_envelope": (I32, [P, I64, I32, P, P, P]),
     "usbf_envelope_iq": (I32, [P, I64, I32, F32, P, I32, F32, I32, P, P, P]),
     "usbf_compound": (I32, [P, I32, I32, I64, P, P]),
+    "usbf_combine_lines": (I32, [P, I32, I32, I64, P, P, I32, I32, P, P]),
     "usbf_log_compress": (I32, [P, I32, I64, F32, F32, P, P, ctypes.c_size_t, P]),
     "usbf_scan_convert": (I32, [P, I32, P, P, P]),
     "usbf_log_scan_convert": (I32, [P, P, I32, P, F32, F32, P, P, ctypes.c_size_t, P]),
@@ -98,7 +99,7 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with python paper_1711_06127_amd/build.py "
-                               "or python paper_1711_06127_amd/build.py")
+                               "(or __graft_entry__.build())")
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             fn = getattr(L, name)
@@ -137,17 +138,21 @@ def _need_cuda(t: torch.Tensor, name: str, dtype=None):
 
 def lines_per_tx_hint(line_tx) -> int:
     """Length of the runs of consecutive lines that share a transmit when all runs have the same
-    length; else the largest G in (8, 4, 2) such that every run of G consecutive lines shares a
-    transmit; else 1."""
+    length; else the largest G in (8, 4, 2) such that in every aligned group of G lines each line
+    that has a transmit (index >= 0) has the transmit of the group's first line (lines without
+    one are zeros and share anything); else 1."""
     lt = np.asarray(line_tx)
     if lt.size:
         change = np.flatnonzero(lt[1:] != lt[:-1])
         run = int(change[0]) + 1 if change.size else int(lt.size)
-        if lt.size % run == 0 and np.all(lt.reshape(-1, run) == lt.reshape(-1, run)[:, :1]):
+        if run > 1 and lt.size % run == 0 and np.all(lt.reshape(-1, run) == lt.reshape(-1, run)[:, :1]):
             return run
     for G in (8, 4, 2):
         n = (lt.size // G) * G
-        if n and np.all(lt[:n].reshape(-1, G) == lt[:n].reshape(-1, G)[:, :1]):
+        if not n:
+            continue
+        t = lt[:n].reshape(-1, G)
+        if np.all((t < 0) | (t == t[:, :1])) and np.all((t[:, 0] >= 0) | np.all(t < 0, axis=1)):
             return G
     return 1
 
@@ -279,6 +284,25 @@ def compound(x: torch.Tensor, n_groups: int, out: torch.Tensor | None = None) ->
     if out is None:
         out = torch.empty((F, x.shape[1] // n_groups, *x.shape[2:]), dtype=torch.float32, device=x.device)
     _check(lib().usbf_compound(_ptr(x), F, n_groups, per // n_groups, _ptr(out), _stream(x.device)))
+    return out
+
+
+def combine_lines(x: torch.Tensor, src: torch.Tensor, w: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Weighted combination of beamformed lines: x [F, n_in, D], src int32 / w float32
+    [n_out, K] (device) -> out [F, n_out, D], out[f, o] = sum_k w[o, k] x[f, src[o, k]]
+    (sources outside [0, n_in) add nothing)."""
+    _need_cuda(x, "x", torch.float32)
+    _need_cuda(src, "src", torch.int32)
+    _need_cuda(w, "w", torch.float32)
+    if src.shape != w.shape or src.dim() != 2:
+        raise ValueError("src and w must both be [n_out, K]")
+    F, n_in = x.shape[0], x.shape[1]
+    length = x.numel() // (F * n_in)
+    n_out, k = src.shape
+    if out is None:
+        out = torch.empty((F, n_out, *x.shape[2:]), dtype=torch.float32, device=x.device)
+    _check(lib().usbf_combine_lines(_ptr(x), F, n_in, length, _ptr(src), _ptr(w), k, n_out, _ptr(out),
+                                    _stream(x.device)))
     return out
 
 

@@ -273,8 +273,10 @@ __device__ __forceinline__ void static_for(F&& f) {
 
 // Delay-and-sum of one tile -- lines [group G, group G + G) x depths [dt TD, dt TD + TD) --
 // for frames [frame0, frame0 + n_blocks * FB) of the batch.  Every lane of the workgroup
-// calls it with the same tile.
-template <bool VEC, int G, int FB, int FS>
+// calls it with the same tile.  SETS: the G slots hold G / n_sets lines x n_sets apodization
+// sets, each slot with its own f-number and window (per-lane values); otherwise all slots
+// take the call's single set from the kernel arguments (wave-uniform scalars).
+template <bool VEC, int G, int FB, int FS, bool SETS = false>
 __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int frame0, int n_blocks, const DasArgs& a,
                                          const TileArgs& ta, float* __restrict__ out, unsigned char* lds_raw,
                                          int group, int dt) {
@@ -288,10 +290,10 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
   const int tid = threadIdx.x;
   // slot g of the tile: line l0 + g % gl with apodization set g / gl (gl = G with one set)
   const int g = tid / TD;
-  const int gl = G / a.n_sets;
+  const int gl = SETS ? G / a.n_sets : G;
   const int l0 = group * gl;
-  const int l = l0 + g % gl;
-  const int set = g / gl;
+  const int l = SETS ? l0 + g % gl : l0 + g;
+  const int set = SETS ? g / gl : 0;
   const int j = dt * TD + tid % TD;
   const int j_first = dt * TD;
   const int j_last = min(a.n_depth, j_first + TD) - 1;
@@ -305,7 +307,7 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
   constexpr int ZERO = SH::BUFV;  // index of a buffer's zero vector
   if (tid < G) {
     line_geom(a, min(l0 + tid % gl, a.n_lines - 1), t.lines[tid]);
-    set_params(a, tid / gl, t.lines[tid]);
+    if (SETS) set_params(a, tid / gl, t.lines[tid]);
   }
   if (tid == 0) {
     V z;
@@ -329,7 +331,7 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
       const float2 E2 = make_float2(E.A, E.B);
       t.geo[gg * a.n_el + e] = E2;
       if (l0 + gg % gl >= a.n_lines || Lg.tx < 0) continue;
-      if (!in_aperture(Lg.F2, a.array_dims, E, r_last)) continue;
+      if (!in_aperture(SETS ? Lg.F2 : a.F2, a.array_dims, E, r_last)) continue;
       const int shift = 8 * (e & 3);
       if (Lg.tx != t_grp) {
         atomicOr(&t.flg[e >> 2], 1 << shift);
@@ -366,7 +368,10 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
   const float r2 = r + r;
   const float rr = r * r;
   const float dtx = small_tx_delay(L, r);
-  const float inv_w = r > 0.0f ? L.fn / r : 0.0f;
+  // apodization of this lane's slot
+  const float ap_F2 = SETS ? L.F2 : a.F2;
+  const int ap_window = SETS ? L.window : a.window;
+  const float inv_w = r > 0.0f ? (SETS ? L.fn : a.f_number) / r : 0.0f;
   const size_t tx_block = size_t(a.n_el) * S;              // samples per transmit
   const size_t frame_stride = size_t(a.n_tx) * tx_block;   // samples per frame
   const int16_t* grp_block = rf + size_t(t_grp < 0 ? 0 : t_grp) * tx_block;
@@ -420,9 +425,9 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
       const float2 E2 = geo[e];
       const float2 xy = t.exy[e];
       const ElemGeom E{E2.x, E2.y, xy.x - L.olx, xy.y - L.oly};
-      const bool act = lane_ok && e0 + k < a.n_el && in_aperture(L.F2, a.array_dims, E, r);
+      const bool act = lane_ok && e0 + k < a.n_el && in_aperture(ap_F2, a.array_dims, E, r);
       if (!__any(act)) continue;  // no lane of the wave needs this element
-      const float w = act ? apod_weight(L.window, a.array_dims, E.dx, E.dy, inv_w) : 0.0f;
+      const float w = act ? apod_weight(ap_window, a.array_dims, E.dx, E.dy, inv_w) : 0.0f;
       den += w;
       const Tap tp = fast_tap(a, b, dtx, E.A, E.B, r, r2, rr);
       const bool ok = act && tp.i0 >= 0 && tp.i0 <= S - 2;
@@ -574,13 +579,13 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
 
 // One workgroup per tile; workgroup ids are remapped so that consecutive depth tiles of a line
 // group run on the same XCD (they share the edges of their channel-data windows in L2).
-template <bool VEC, int G, int FB, int FS>
+template <bool VEC, int G, int FB, int FS, bool SETS>
 __global__ __launch_bounds__(kDasThreads) void das_tile_kernel(const int16_t* __restrict__ rf, int frame0,
                                                                int n_blocks, DasArgs a, TileArgs ta,
                                                                float* __restrict__ out) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const uint32_t bid = xcd_swizzle(blockIdx.x, gridDim.x);
-  das_tile<VEC, G, FB, FS>(rf, frame0, n_blocks, a, ta, out, lds_raw, int(bid / ta.n_dtiles),
+  das_tile<VEC, G, FB, FS, SETS>(rf, frame0, n_blocks, a, ta, out, lds_raw, int(bid / ta.n_dtiles),
                            int(bid % ta.n_dtiles));
 }
 
@@ -654,7 +659,7 @@ static int allow_lds(const void* kernel, size_t lds) {
   return USBF_OK;
 }
 
-template <int G, int FB, int FS>
+template <int G, int FB, int FS, bool SETS>
 static int launch_das(const int16_t* rf, int frame0, int n_blocks, const DasArgs& a, float* out, hipStream_t s) {
   using SH = Shape<G, FS>;
   TileArgs ta;
@@ -666,7 +671,7 @@ static int launch_das(const int16_t* rf, int frame0, int n_blocks, const DasArgs
   }
   ta.pshift = (a.depth_step % 2 == 0) ? 1 : 0;
   ta.n_dtiles = (a.n_depth + SH::TD - 1) / SH::TD;
-  const int gl = G / a.n_sets;  // lines per tile
+  const int gl = SETS ? G / a.n_sets : G;  // lines per tile
   const int64_t blocks = int64_t((a.n_lines + gl - 1) / gl) * ta.n_dtiles;
   if (blocks > 0x7fffffff) return fail(USBF_EUNSUPPORTED, "too many tiles");
   const size_t lds = tile_lds_bytes<G, FS>(a.n_el);
@@ -674,12 +679,12 @@ static int launch_das(const int16_t* rf, int frame0, int n_blocks, const DasArgs
     return fail(USBF_EUNSUPPORTED, "%d elements need %zu bytes of LDS per tile", a.n_el, lds);
   const bool vec = (a.n_samples % 4) == 0 && (reinterpret_cast<uintptr_t>(rf) & 7) == 0;
   if (vec) {
-    if (lds > 65536 && allow_lds((const void*)das_tile_kernel<true, G, FB, FS>, lds)) return USBF_EDEVICE;
-    hipLaunchKernelGGL((das_tile_kernel<true, G, FB, FS>), dim3(unsigned(blocks)), dim3(kDasThreads), lds, s, rf,
+    if (lds > 65536 && allow_lds((const void*)das_tile_kernel<true, G, FB, FS, SETS>, lds)) return USBF_EDEVICE;
+    hipLaunchKernelGGL((das_tile_kernel<true, G, FB, FS, SETS>), dim3(unsigned(blocks)), dim3(kDasThreads), lds, s, rf,
                        frame0, n_blocks, a, ta, out);
   } else {
-    if (lds > 65536 && allow_lds((const void*)das_tile_kernel<false, G, FB, FS>, lds)) return USBF_EDEVICE;
-    hipLaunchKernelGGL((das_tile_kernel<false, G, FB, FS>), dim3(unsigned(blocks)), dim3(kDasThreads), lds, s, rf,
+    if (lds > 65536 && allow_lds((const void*)das_tile_kernel<false, G, FB, FS, SETS>, lds)) return USBF_EDEVICE;
+    hipLaunchKernelGGL((das_tile_kernel<false, G, FB, FS, SETS>), dim3(unsigned(blocks)), dim3(kDasThreads), lds, s, rf,
                        frame0, n_blocks, a, ta, out);
   }
   return check_launch("das_tile_kernel");
@@ -687,7 +692,7 @@ static int launch_das(const int16_t* rf, int frame0, int n_blocks, const DasArgs
 
 // Frames are processed in blocks of FB sharing one evaluation of the delays; the batch is
 // split into launches of whole blocks, largest first (e.g. 37 = 32 + 4 + 1).
-template <int G>
+template <int G, bool SETS>
 static int launch_das_g(const int16_t* rf, int n_frames, const DasArgs& a, float* out, hipStream_t s) {
   int f0 = 0, st = USBF_OK;
   const uint64_t frame_bytes = uint64_t(a.n_tx) * a.n_el * a.n_samples * sizeof(int16_t);
@@ -700,12 +705,12 @@ static int launch_das_g(const int16_t* rf, int n_frames, const DasArgs& a, float
       f0 += nb * FB;
     }
   };
-  run(32, [&](int f, int nb) { return launch_das<G, 32, 4>(rf, f, nb, a, out, s); });
-  run(16, [&](int f, int nb) { return launch_das<G, 16, 4>(rf, f, nb, a, out, s); });
-  run(8, [&](int f, int nb) { return launch_das<G, 8, 4>(rf, f, nb, a, out, s); });
-  run(4, [&](int f, int nb) { return launch_das<G, 4, 4>(rf, f, nb, a, out, s); });
-  run(2, [&](int f, int nb) { return launch_das<G, 2, 2>(rf, f, nb, a, out, s); });
-  run(1, [&](int f, int nb) { return launch_das<G, 1, 1>(rf, f, nb, a, out, s); });
+  run(32, [&](int f, int nb) { return launch_das<G, 32, 4, SETS>(rf, f, nb, a, out, s); });
+  run(16, [&](int f, int nb) { return launch_das<G, 16, 4, SETS>(rf, f, nb, a, out, s); });
+  run(8, [&](int f, int nb) { return launch_das<G, 8, 4, SETS>(rf, f, nb, a, out, s); });
+  run(4, [&](int f, int nb) { return launch_das<G, 4, 4, SETS>(rf, f, nb, a, out, s); });
+  run(2, [&](int f, int nb) { return launch_das<G, 2, 2, SETS>(rf, f, nb, a, out, s); });
+  run(1, [&](int f, int nb) { return launch_das<G, 1, 1, SETS>(rf, f, nb, a, out, s); });
   return st;
 }
 
@@ -767,11 +772,18 @@ int beamform_enqueue(const int16_t* rf, int32_t n_frames, const DasArgs& a, floa
   const int lpt = a.lines_per_tx;
   int gl = lpt == 8 ? 8 : (lpt >= 4 && lpt % 4 == 0) ? 4 : (lpt >= 2 && lpt % 2 == 0) ? 2 : 1;
   while (gl > 1 && gl * a.n_sets > 8) gl >>= 1;
-  switch (gl * a.n_sets) {
-    case 8: return launch_das_g<8>(rf, n_frames, a, out, s);
-    case 4: return launch_das_g<4>(rf, n_frames, a, out, s);
-    case 2: return launch_das_g<2>(rf, n_frames, a, out, s);
-    default: return launch_das_g<1>(rf, n_frames, a, out, s);
+  if (a.n_sets > 1) {
+    switch (gl * a.n_sets) {
+      case 8: return launch_das_g<8, true>(rf, n_frames, a, out, s);
+      case 4: return launch_das_g<4, true>(rf, n_frames, a, out, s);
+      default: return launch_das_g<2, true>(rf, n_frames, a, out, s);
+    }
+  }
+  switch (gl) {
+    case 8: return launch_das_g<8, false>(rf, n_frames, a, out, s);
+    case 4: return launch_das_g<4, false>(rf, n_frames, a, out, s);
+    case 2: return launch_das_g<2, false>(rf, n_frames, a, out, s);
+    default: return launch_das_g<1, false>(rf, n_frames, a, out, s);
   }
 }
 

@@ -288,3 +288,53 @@ def config_planewave_2d(n_el: int = 128, n_angles: int = 11, max_angle_deg: floa
     g.scan = scan_grid_2d(lx, 0.0, depth_step * h, n_depth, nx=scan_n[0], nz=scan_n[1])
     g.n_angles = n_angles
     return g
+
+
+def config_overlap_2d(n_el: int = 128, n_samples: int = 4096, pitch: float = 0.3e-3, focus: float = 30e-3,
+                      scan_n=(512, 512)) -> Geometry:
+    """128 transmits, 255 lines: the overlapping multi-line layout.  Transmit t is focused along
+    element t's axis; the 2 n_el - 1 output lines lie at half pitch from the first element to the
+    last.  Line 2t (on transmit t's axis) is transmit t's beam; line 2t + 1 (half way to the next
+    transmit) is the mean of the beams of transmits t and t + 1 (linear interpolation between
+    the two nearest transmits).  The geometry holds the beams to form: four line slots per
+    transmit -- lines 2t, 2t - 1, 2t + 1 and an unused slot (transmit -1, a line of zeros), so
+    that every tile of four slots shares one transmit's channel data -- and `combine_src` /
+    `combine_w` ([2 n_el - 1][2]) say which beams make each output line, with which weight
+    (a source of -1 contributes nothing)."""
+    x_t = (np.arange(n_el, dtype=np.float64) - (n_el - 1) / 2.0) * pitch
+    n_out = 2 * n_el - 1
+    x_m = x_t[0] + np.arange(n_out) * (pitch / 2.0)
+    slots = np.full((n_el, 4), -1, dtype=np.int64)  # output line of each slot, -1 unused
+    for t in range(n_el):
+        for k, m in enumerate((2 * t, 2 * t - 1, 2 * t + 1)):
+            if 0 <= m < n_out:
+                slots[t, k] = m
+    n_lines = 4 * n_el
+    lx = np.where(slots.ravel() >= 0, x_m[np.clip(slots.ravel(), 0, n_out - 1)], np.repeat(x_t, 4))
+    line_origin = _f32(np.stack([lx, np.zeros(n_lines), np.zeros(n_lines)], axis=1))
+    line_dir = _f32(np.tile([0.0, 0.0, 1.0], (n_lines, 1)))
+    line_tx = np.where(slots.ravel() >= 0, np.repeat(np.arange(n_el), 4), -1).astype(np.int32)
+    src = np.full((n_out, 2), -1, dtype=np.int32)
+    w = np.zeros((n_out, 2), dtype=np.float32)
+    for m in range(n_out):
+        t = m // 2
+        if m % 2 == 0:
+            src[m, 0], w[m, 0] = 4 * t, 1.0
+        else:
+            src[m] = (4 * t + 2, 4 * (t + 1) + 1)
+            w[m] = (0.5, 0.5)
+    depth_step = 2
+    n_depth = n_samples // depth_step
+    c, fs = 1540.0, 40e6
+    g = Geometry(name=f"overlap{n_el}tx_{n_out}lines_{n_samples}", el_pos=linear_array(n_el, pitch),
+                 tx_origin=_f32(np.stack([x_t, np.zeros(n_el), np.zeros(n_el)], axis=1)),
+                 tx_dir=_f32(np.tile([0.0, 0.0, 1.0], (n_el, 1))), tx_focus=_f32(np.full(n_el, focus)),
+                 line_origin=line_origin, line_dir=line_dir, line_tx=np.ascontiguousarray(line_tx), array_dims=1,
+                 c=float(np.float32(c)), fs=float(np.float32(fs)), t0=0.0, n_samples=n_samples,
+                 depth_start=0, depth_step=depth_step, n_depth=n_depth, f_number=1.0, window=HANN, f0=5e6)
+    h = float(np.float32(c)) / (2.0 * float(np.float32(fs)))
+    g.scan = scan_grid_2d(x_m, 0.0, depth_step * h, n_depth, nx=scan_n[0], nz=scan_n[1])
+    g.combine_src, g.combine_w = src, w
+    g.n_out_lines = n_out
+    g.out_line_x = x_m
+    return g

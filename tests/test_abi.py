@@ -104,6 +104,18 @@ def test_beamform_sets_rejects(u):
     assert call(2, [1.0, 2.0], [1, 1], frames=0) == -1
 
 
+def test_combine_lines_rejects(u):
+    L = u.lib()
+    assert L.usbf_combine_lines(None, 1, 4, 10, FAKE, FAKE, 2, 3, FAKE, None) == -1
+    assert L.usbf_combine_lines(FAKE, 0, 4, 10, FAKE, FAKE, 2, 3, FAKE + (1 << 20), None) == -1
+    assert L.usbf_combine_lines(FAKE, 1, 4, 0, FAKE, FAKE, 2, 3, FAKE + (1 << 20), None) == -1
+    assert L.usbf_combine_lines(FAKE, 1, 4, 10, FAKE, FAKE, 0, 3, FAKE + (1 << 20), None) == -3
+    assert L.usbf_combine_lines(FAKE, 1, 4, 10, FAKE, FAKE, 65, 3, FAKE + (1 << 20), None) == -3
+    assert L.usbf_combine_lines(FAKE, 1, 4, 10, FAKE, FAKE, 2, 0, FAKE + (1 << 20), None) == -1
+    # out inside the input
+    assert L.usbf_combine_lines(FAKE, 1, 4, 10, FAKE, FAKE, 2, 3, FAKE + 8, None) == -1
+
+
 def test_envelope_and_log_reject(u):
     L = u.lib()
     assert L.usbf_envelope(FAKE, 4, 4, FAKE, None, None) == -3            # too short
@@ -218,3 +230,20 @@ def test_compound_rejects(u):
     assert L.usbf_compound(FAKE, 0, 2, 100, FAKE + 4096, None) == -1
     assert L.usbf_compound(FAKE, 1, 0, 100, FAKE + 4096, None) == -1
     assert L.usbf_compound(FAKE, 1, 2, 100, FAKE + 400, None) == -1   # out inside the input
+
+
+def test_lines_per_tx_hint(u):
+    """Tiles of G lines share one staging of a transmit's channel data when every line of the
+    group that has a transmit has the group's first line's transmit."""
+    import numpy as np
+    import synth
+    h = u.lines_per_tx_hint
+    assert h(synth.config_multiline_2d().line_tx) == 4
+    assert h(synth.config_small_2d().line_tx) == 1
+    assert h(synth.config_planewave_2d(lines=64, n_samples=256).line_tx) == 64
+    assert h(synth.config_overlap_2d(n_el=16, n_samples=256).line_tx) == 4
+    assert h(np.array([0, 1, 1, 1, 1])) == 1
+    assert h(np.array([0, 0, 1, 1, 2, 2, 3])) == 2
+    assert h(np.array([-1, -1, -1, -1, 0, 0, 0, 0])) == 4
+    assert h(np.array([0, -1, 0, -1, 1, 1, 1, -1])) == 4
+    assert h(np.array([-1, 0, 0, 0, 1, 1, 1, 1])) == 1
