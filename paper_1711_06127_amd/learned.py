@@ -11,7 +11,9 @@ weighted sum, envelope and compression -- runs in the library's HIP kernels; thi
 schedules them and measures the resulting images.
 
 Image measures: contrast-to-noise ratio of anechoic cysts, |mu_in - mu_out| / sqrt(var_in +
-var_out) of the envelope, and the lateral -6 dB width of point-target responses.
+var_out) of the envelope inside 0.75 R against the ring 1.25 R .. 1.75 R, and the lateral -6 dB
+width of point-target responses, measured on an auxiliary set of lines a twentieth of a
+wavelength apart through each target.
 
 Run ``python -m paper_1711_06127_amd.learned`` on a GPU to train and compare the three
 beamformers on held-out phantoms (prints one JSON line).
@@ -19,6 +21,7 @@ beamformers on held-out phantoms (prints one JSON line).
 from __future__ import annotations
 
 import argparse
+import copy
 import json
 import time
 
@@ -147,15 +150,45 @@ def psf_widths(env: np.ndarray, line_x: np.ndarray, targets) -> np.ndarray:
 
 
 def cnr(env: np.ndarray, line_x: np.ndarray, depth_z: np.ndarray, cysts) -> np.ndarray:
-    """Contrast-to-noise ratio of each cyst (cx, cz, r): inside 0.8 r against the ring 1.2 r..1.8 r."""
+    """Contrast-to-noise ratio of each cyst (cx, cz, r): inside 0.75 r against the ring
+    1.25 r .. 1.75 r."""
     X, Z = np.meshgrid(line_x, depth_z, indexing="ij")
     out = []
     for (cx, cz, r) in cysts:
         d2 = (X - cx) ** 2 + (Z - cz) ** 2
-        inside = env[d2 <= (0.8 * r) ** 2]
-        ring = env[(d2 >= (1.2 * r) ** 2) & (d2 <= (1.8 * r) ** 2)]
+        inside = env[d2 <= (0.75 * r) ** 2]
+        ring = env[(d2 >= (1.25 * r) ** 2) & (d2 <= (1.75 * r) ** 2)]
         out.append(abs(inside.mean() - ring.mean()) / np.sqrt(inside.var() + ring.var()))
     return np.array(out)
+
+
+def aux_geometry(g, xs):
+    """Vertical lines from the array plane at lateral positions xs, on g's depth grid; each
+    line takes the transmit whose origin is laterally nearest (the transmit that would fire
+    for a line there)."""
+    xs = np.asarray(xs, np.float64)
+    n = xs.size
+    a = copy.copy(g)
+    a.line_origin = np.ascontiguousarray(np.stack([xs, np.zeros(n), np.zeros(n)], 1).astype(np.float32))
+    a.line_dir = np.ascontiguousarray(np.tile(np.float32([0.0, 0.0, 1.0]), (n, 1)))
+    tx_x = np.asarray(g.tx_origin[:, 0], np.float64)
+    a.line_tx = np.ascontiguousarray(np.argmin(np.abs(xs[:, None] - tx_x[None, :]), axis=1).astype(np.int32))
+    a.scan = None
+    return a
+
+
+def psf_widths_fine(rf: torch.Tensor, g, method: str, model=None, targets=(), half_width: float = 1.5e-3,
+                    device="cuda") -> np.ndarray:
+    """Lateral -6 dB width (metres) of each point target (line, depth) of g, measured on lines
+    spaced a twentieth of the wavelength c / f0 within +-half_width of the target's line."""
+    step = g.c / g.f0 / 20.0
+    offs = np.arange(-round(half_width / step), round(half_width / step) + 1) * step
+    x0 = np.asarray(g.line_origin[:, 0], np.float64)
+    xs = np.concatenate([x0[l] + offs for (l, _) in targets])
+    dg = DeviceGeometry(aux_geometry(g, xs), device)
+    env = frame_envelope(beamform_lines(rf, dg, method, model))
+    n, c = offs.size, offs.size // 2
+    return np.array([psf_widths(env[k * n:(k + 1) * n], offs, [(c, j)])[0] for k, (_, j) in enumerate(targets)])
 
 
 def _sim(g, seed, cysts=(), n_speckle=5000, device="cuda"):
@@ -164,24 +197,52 @@ def _sim(g, seed, cysts=(), n_speckle=5000, device="cuda"):
     return synth.rfsim.simulate_frame(g, pos, amp, seed, device=device).contiguous(), lj
 
 
-def evaluate(model: LearnedApodization, g, dg: DeviceGeometry, seed: int = 900) -> dict:
-    """CNR on a cyst phantom and -6 dB widths on a sparse point phantom for DAS, MV and the
-    network, plus the GPU time of the MV and network weight paths for one frame."""
+def eval_phantom(g, seed: int, device="cuda"):
+    """A held-out frame: speckle, one anechoic cyst of radius 4 mm at (0, 40 mm) and 8 point
+    targets from 15 to 70 mm deep, alternately 6 mm left and right of the centre, each moved
+    onto the nearest output pixel.  Returns (rf, cyst, point pixels)."""
+    import synth  # seeded input generation (synthetic phantoms)
+    lx = np.asarray(g.line_origin[:, 0], np.float64)
+    dz = float(g.depth_of(1) - g.depth_of(0))
+    cyst = (0.0, 40e-3, 4e-3)
+    pts, lj = [], []
+    for k, z in enumerate(np.linspace(15e-3, 70e-3, 8)):
+        l = int(np.argmin(np.abs(lx - (6e-3 if k % 2 else -6e-3))))
+        j = int(round(z / dz))
+        p = synth.phantom.pixel_position(g, l, j)
+        pts.append((float(p[0]), float(p[2]), 10.0))
+        lj.append((l, j))
+    pos, amp, _ = synth.phantom.phantom_2d(g, seed, n_points=False, cysts=[cyst], extra_points=pts)
+    rf = synth.rfsim.simulate_frame(g, pos, amp, seed, device=device).contiguous()
+    return rf, cyst, lj
+
+
+def evaluate(model: LearnedApodization, g, dg: DeviceGeometry, n_frames: int = 32, seed: int = 90000) -> dict:
+    """Mean CNR of the cyst and mean -6 dB width of the points over n_frames held-out frames for
+    DAS, MV and the network; the network passes if its mean CNR and mean width are both within
+    10 % of MV's and its mean width is narrower than DAS's.  Also the GPU time of the MV and
+    network weight paths for one frame's pixels."""
     lx = g.line_origin[:, 0].astype(np.float64)
     z = np.array([g.depth_of(j) for j in range(g.n_depth)], dtype=np.float64)
-    span = lx[-1] - lx[0]
-    cysts = [(-0.2 * span, 0.3 * z[-1], 3e-3), (0.2 * span, 0.5 * z[-1], 4e-3)]
-    rf_c, _ = _sim(g, seed, cysts=cysts)
-    rf_p, lj = _sim(g, seed + 1, n_speckle=200)
-    res = {}
-    for m in ("das", "mv", "learned"):
-        env_c = frame_envelope(beamform_lines(rf_c, dg, m, model))
-        env_p = frame_envelope(beamform_lines(rf_p, dg, m, model))
-        res[m] = {"cnr": cnr(env_c, lx, z, cysts).tolist(),
-                  "psf_width_mm": (psf_widths(env_p, lx, lj) * 1e3).tolist()}
+    c = {m: [] for m in ("das", "mv", "learned")}
+    w = {m: [] for m in ("das", "mv", "learned")}
+    for f in range(n_frames):
+        rf, cyst, lj = eval_phantom(g, seed + f, dg.device)
+        for m in c:
+            env = frame_envelope(beamform_lines(rf, dg, m, model))
+            c[m].append(float(cnr(env, lx, z, [cyst])[0]))
+            w[m].extend((psf_widths_fine(rf, g, m, model, lj, device=dg.device) * 1e3).tolist())
+    res = {m: {"cnr_mean": float(np.mean(c[m])), "cnr_std": float(np.std(c[m])),
+               "psf_width_mm_mean": float(np.mean(w[m])), "psf_width_mm_std": float(np.std(w[m]))} for m in c}
+    dc = res["learned"]["cnr_mean"] / res["mv"]["cnr_mean"] - 1.0
+    dw = res["learned"]["psf_width_mm_mean"] / res["mv"]["psf_width_mm_mean"] - 1.0
+    res["learned_vs_mv"] = {"cnr_rel": dc, "width_rel": dw,
+                            "pass": bool(abs(dc) <= 0.1 and abs(dw) <= 0.1 and
+                                         res["learned"]["psf_width_mm_mean"] < res["das"]["psf_width_mm_mean"])}
     # weight-path timing on one full frame (gather excluded: both need it)
-    pix = frame_pixels(dg.n_lines, dg.n_depth, 0, rf_c.device)[:262144]
-    x = delay_gather(rf_c, dg, pix)
+    rf, _, _ = eval_phantom(g, seed, dg.device)
+    pix = frame_pixels(dg.n_lines, dg.n_depth, 0, rf.device)[:262144]
+    x = delay_gather(rf, dg, pix)
     for name, fn in (("mv", lambda: mv_weights(x, SUBAPERTURE, LOADING)),
                      ("learned", lambda: model.weights(x))):
         fn()
@@ -193,6 +254,7 @@ def evaluate(model: LearnedApodization, g, dg: DeviceGeometry, seed: int = 900) 
         e1.record()
         torch.cuda.synchronize()
         res[name]["weights_ms_per_262144_px"] = e0.elapsed_time(e1) / 5
+    res["eval"] = f"{n_frames} held-out frames (seeds {seed}..), 1 cyst and 8 points each"
     return res
 
 
@@ -203,6 +265,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--eval-frames", type=int, default=32)
     ap.add_argument("--save", default="")
     args = ap.parse_args()
     g = synth.config_multiline_2d()
@@ -224,7 +287,7 @@ def main():
     hist = model.train(rf, dg, args.steps, args.batch, args.lr, log_every=max(1, args.steps // 20))
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t
-    res = evaluate(model, g, dg)
+    res = evaluate(model, g, dg, n_frames=args.eval_frames)
     if args.save:
         np.savez(args.save, **model.net.params())
     print(json.dumps({"train_frames": args.frames, "steps": args.steps, "batch": args.batch, "sim_s": t_sim,

@@ -51,3 +51,33 @@ def test_initial_network_is_near_uniform():
     p = L.init_params(0, 128)
     assert p["b4"][0] == np.float32(1 / 128)
     assert np.abs(p["W4"]).max() <= 1e-3 * np.sqrt(6 / 160) + 1e-9
+
+
+def test_auxiliary_lines_take_the_nearest_transmit():
+    import synth
+    g = synth.config_multiline_2d()
+    tx_x = g.tx_origin[:, 0].astype(np.float64)
+    xs = np.array([tx_x[0] - 1e-3, tx_x[10] + 1e-5, 0.5 * (tx_x[20] + tx_x[21]) - 1e-6, tx_x[-1] + 2e-3])
+    a = L.aux_geometry(g, xs)
+    assert a.line_tx.tolist() == [0, 10, 20, 63]
+    np.testing.assert_allclose(a.line_origin[:, 0], xs.astype(np.float32))
+    assert np.all(a.line_dir == np.float32([0, 0, 1])) and a.n_lines == 4
+    assert a.n_depth == g.n_depth and a.tx_origin is g.tx_origin
+
+
+def test_cnr_regions_are_three_quarters_and_the_ring():
+    """Inside 0.75 R against 1.25 R .. 1.75 R: a cyst whose edge zone (0.75 R .. 1.25 R) holds
+    outliers does not change the measure."""
+    lx = np.linspace(-10e-3, 10e-3, 401)
+    z = np.linspace(0, 40e-3, 801)
+    X, Z = np.meshgrid(lx, z, indexing="ij")
+    d2 = X ** 2 + (Z - 20e-3) ** 2
+    R = 4e-3
+    inside = d2 <= (0.75 * R) ** 2
+    ring_m = (d2 >= (1.25 * R) ** 2) & (d2 <= (1.75 * R) ** 2)
+    env = np.where(inside, 0.0, 1.0) + np.where(ring_m, (X > 0) * 1.0, 0.0)
+    env = np.where(~inside & (d2 < (1.25 * R) ** 2), 100.0, env)
+    c = L.cnr(env, lx, z, [(0.0, 20e-3, R)])
+    ring = env[ring_m]
+    exact = abs(0.0 - ring.mean()) / np.sqrt(0.0 + ring.var())
+    assert abs(c[0] - exact) < 1e-12
