@@ -15,6 +15,12 @@ smoothed, diagonally loaded estimator of Synnevaag, Austeng and Holm (2007):
   y      = w_full^T x = (1/K) sum_l w^T x_l
 
 Everything is float64; numpy's Cholesky and triangular solves are the library steps.
+
+Temporal averaging (a common refinement of the same estimator, not in the paper): the
+covariance also averages over T neighbouring depth samples of the pixel's line,
+  R = (1/(T K)) sum_tau sum_l x_{tau,l} x_{tau,l}^T,
+with x_tau the delayed samples at depth j + tau - (T-1)/2 (T odd); the weights then apply to
+the pixel's own samples (tau = (T-1)/2).
 """
 from __future__ import annotations
 
@@ -32,6 +38,17 @@ def covariance(x: np.ndarray, L: int) -> np.ndarray:
         xl = x[:, l:l + L]
         R += xl[:, :, None] * xl[:, None, :]
     return R / K
+
+
+def covariance_averaged(x: np.ndarray, L: int) -> np.ndarray:
+    """Spatially and temporally smoothed covariance, x: [P, T, M] -> [P, L, L]: the mean of the
+    per-depth smoothed covariances."""
+    x = np.asarray(x, dtype=np.float64)
+    P, T, M = x.shape
+    R = np.zeros((P, L, L))
+    for t in range(T):
+        R += covariance(x[:, t], L)
+    return R / T
 
 
 def loaded(R: np.ndarray, loading: float) -> np.ndarray:
@@ -73,4 +90,16 @@ def mv_weights(x: np.ndarray, L: int = 32, loading: float = 1e-2):
     w = v / v.sum(axis=1, keepdims=True)
     wf = expand(w, x.shape[1])
     y = np.einsum("pm,pm->p", wf, x)
+    return wf, y, w
+
+
+def mv_weights_averaged(x: np.ndarray, L: int = 32, loading: float = 1e-2):
+    """Minimum variance with temporal averaging: x [P, T, M] (T odd, the pixel's own samples
+    in the middle row) -> (w_full [P, M], y [P], w [P, L])."""
+    x = np.asarray(x, dtype=np.float64)
+    A = loaded(covariance_averaged(x, L), loading)
+    v = solve_ones(A)
+    w = v / v.sum(axis=1, keepdims=True)
+    wf = expand(w, x.shape[2])
+    y = np.einsum("pm,pm->p", wf, x[:, x.shape[1] // 2])
     return wf, y, w
