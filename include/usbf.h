@@ -296,6 +296,19 @@ int usbf_mv_weights(const float* x, int32_t n_pix, int32_t n_el, int32_t subap, 
                     float* w_full, float* y, hipStream_t stream);
 
 /*
+ * Minimum variance with temporal averaging (the same estimator, not in the paper): the
+ * covariance also averages over n_avg neighbouring depth samples of the pixel's line,
+ *   R = (1/(n_avg K)) sum_t sum_l x_{t,l} x_{t,l}^T   (binary32, rows in order t = 0 ..),
+ * and the weights apply to the middle row, y = w_full^T x_{n_avg/2}.  Loading, solve and
+ * expansion as usbf_mv_weights(), which is the case n_avg = 1 (bit for bit).
+ *   x  float [n_pix][n_avg][n_el]: for each pixel the delayed samples at n_avg consecutive
+ *      depths (how the edges of a line are handled is the caller's choice);
+ *   n_avg odd, 1..255; other arguments as usbf_mv_weights().
+ */
+int usbf_mv_weights_averaged(const float* x, int32_t n_pix, int32_t n_avg, int32_t n_el, int32_t subap,
+                             float loading, float* w_full, float* y, hipStream_t stream);
+
+/*
  * Learned apodization: a 1D convolutional network -- four layers, 32 channels, kernel 5,
  * ReLU between layers, "same" zero padding -- maps the delayed samples x of a pixel
  * (normalised by their RMS) to one weight per element; trained to reproduce minimum-variance

@@ -72,6 +72,7 @@ _SIGS = {
     "usbf_scan_index_map": (I32, [P, P, P]),
     "usbf_delay_gather": (I32, [P, I32, P, P, P, I32, P, P]),
     "usbf_mv_weights": (I32, [P, I32, I32, I32, F32, P, P, P]),
+    "usbf_mv_weights_averaged": (I32, [P, I32, I32, I32, I32, F32, P, P, P]),
     "usbf_apodnet_state_bytes": (ctypes.c_size_t, []),
     "usbf_apodnet_num_params": (I32, []),
     "usbf_apodnet_init": (I32, [P, P, P]),
@@ -410,6 +411,26 @@ def mv_weights(x: torch.Tensor, subap: int = 32, loading: float = 1e-2, want_wei
     y = torch.empty(n, dtype=torch.float32, device=x.device)
     _check(lib().usbf_mv_weights(_ptr(x), n, m, subap, loading, _ptr(wf), _ptr(y), _stream(x.device)))
     return wf, y
+
+
+def mv_weights_averaged(x: torch.Tensor, subap: int = 32, loading: float = 1e-2, want_weights: bool = True):
+    """Minimum variance with the covariance averaged over depths: x [n_pix, n_avg, n_el]
+    (n_avg odd; the pixel's own samples in the middle row) -> (w_full or None, y)."""
+    _need_cuda(x, "x", torch.float32)
+    n, t, m = x.shape
+    wf = torch.empty((n, m), dtype=torch.float32, device=x.device) if want_weights else None
+    y = torch.empty(n, dtype=torch.float32, device=x.device)
+    _check(lib().usbf_mv_weights_averaged(_ptr(x), n, t, m, subap, loading, _ptr(wf), _ptr(y), _stream(x.device)))
+    return wf, y
+
+
+def depth_neighbours(pix: torch.Tensor, n_avg: int, n_depth: int) -> torch.Tensor:
+    """Pixel list [n, 3] (frame, line, depth) -> [n * n_avg, 3]: for each pixel the n_avg
+    depths centred on it, clamped to the line (the edge sample repeats)."""
+    off = torch.arange(n_avg, device=pix.device, dtype=torch.int32) - n_avg // 2
+    p = pix[:, None, :].repeat(1, n_avg, 1)
+    p[:, :, 2] = (p[:, :, 2] + off[None, :]).clamp(0, n_depth - 1)
+    return p.reshape(-1, 3).contiguous()
 
 
 OP_APODNET_TRAIN = 6

@@ -85,7 +85,11 @@ __device__ inline double shfl32(double v, int src) {
   return __shfl(v, src, 32);
 }
 
-__global__ __launch_bounds__(64) void mv_kernel(const float* __restrict__ xin, int n_pix, int M, float loading,
+// x: [n_pix][T][M]; the covariance averages the T rows (neighbouring depths), the weights
+// apply to row T / 2 (the pixel's own samples).  AVG = false: T = 1, plain spatial smoothing
+// (the same arithmetic without the row loop).
+template <bool AVG>
+__global__ __launch_bounds__(64) void mv_kernel(const float* __restrict__ xin, int n_pix, int T, int M, float loading,
                                                 float* __restrict__ w_full, float* __restrict__ y) {
   __shared__ MvLds lds[kMvPixPerBlock];
   const int half = threadIdx.x / kMvL;
@@ -94,13 +98,14 @@ __global__ __launch_bounds__(64) void mv_kernel(const float* __restrict__ xin, i
   const bool ok = p < n_pix;
   MvLds& s = lds[half];
   const int K = M - kMvL + 1;
-  const float* xp = xin + size_t(ok ? p : 0) * M;
-  for (int e = i; e < M; e += kMvL) s.x[e] = ok ? xp[e] : 0.0f;
-  __syncthreads();
+  const float* xp = xin + size_t(ok ? p : 0) * T * M;
 
-  // spatially smoothed covariance: lane d sweeps the d-th diagonal,
-  // S_d(a) = sum_{k=a}^{a+K-1} x[k] x[k+d], R[a][a+d] = R[a+d][a] = S_d(a) / K
-  {
+  // spatially smoothed covariance of each row: lane d sweeps the d-th diagonal,
+  // S_d(a) = sum_{k=a}^{a+K-1} x[k] x[k+d], summed over the rows into R[a][a+d] = R[a+d][a],
+  // then divided by T K
+  if constexpr (!AVG) {
+    for (int e = i; e < M; e += kMvL) s.x[e] = ok ? xp[e] : 0.0f;
+    __syncthreads();
     const int d = i;
     float S = 0.0f;
     for (int k = 0; k < K; ++k) S = __builtin_fmaf(s.x[k], s.x[k + d], S);
@@ -111,6 +116,34 @@ __global__ __launch_bounds__(64) void mv_kernel(const float* __restrict__ xin, i
       s.R[a0 + d][a0] = v;
       if (a0 + d + 1 < kMvL)
         S = __builtin_fmaf(s.x[a0 + K], s.x[a0 + K + d], __builtin_fmaf(-s.x[a0], s.x[a0 + d], S));
+    }
+  } else {
+    for (int a0 = 0; a0 + i < kMvL; ++a0) s.R[a0][a0 + i] = 0.0f;
+    for (int t = 0; t < T; ++t) {
+      __syncthreads();  // the previous row's sweep is done with s.x
+      for (int e = i; e < M; e += kMvL) s.x[e] = ok ? xp[size_t(t) * M + e] : 0.0f;
+      __syncthreads();
+      const int d = i;
+      float S = 0.0f;
+      for (int k = 0; k < K; ++k) S = __builtin_fmaf(s.x[k], s.x[k + d], S);
+      for (int a0 = 0; a0 + d < kMvL; ++a0) {
+        s.R[a0][a0 + d] += S;
+        if (a0 + d + 1 < kMvL)
+          S = __builtin_fmaf(s.x[a0 + K], s.x[a0 + K + d], __builtin_fmaf(-s.x[a0], s.x[a0 + d], S));
+      }
+    }
+    {
+      const float inv = 1.0f / (float(K) * float(T));
+      for (int a0 = 0; a0 + i < kMvL; ++a0) {
+        const float v = s.R[a0][a0 + i] * inv;
+        s.R[a0][a0 + i] = v;
+        s.R[a0 + i][a0] = v;
+      }
+    }
+    // the pixel's own samples for the output
+    if (T > 1) {
+      __syncthreads();
+      for (int e = i; e < M; e += kMvL) s.x[e] = ok ? xp[size_t(T / 2) * M + e] : 0.0f;
     }
   }
   __syncthreads();
@@ -203,15 +236,30 @@ extern "C" int usbf_delay_gather(const int16_t* rf, int32_t n_frames, const usbf
   return check_launch("gather_kernel");
 }
 
-extern "C" int usbf_mv_weights(const float* x, int32_t n_pix, int32_t n_el, int32_t subap, float loading,
-                               float* w_full, float* y, hipStream_t stream) {
+static int mv_launch(const float* x, int32_t n_pix, int32_t n_avg, int32_t n_el, int32_t subap, float loading,
+                     float* w_full, float* y, hipStream_t stream) {
   USBF_REQUIRE(x && (w_full || y), USBF_EINVAL, "null x, or neither w_full nor y requested");
   USBF_REQUIRE(n_pix >= 1, USBF_EINVAL, "n_pix must be >= 1");
+  USBF_REQUIRE(n_avg >= 1 && n_avg <= 255 && n_avg % 2 == 1, USBF_EINVAL, "n_avg %d: must be odd in 1..255", n_avg);
   USBF_REQUIRE(subap == kMvL, USBF_EUNSUPPORTED, "subaperture %d: only %d is implemented", subap, kMvL);
   USBF_REQUIRE(n_el >= subap && n_el <= kMvMaxEl, USBF_EUNSUPPORTED, "n_el %d outside %d..%d", n_el, subap,
                kMvMaxEl);
   USBF_REQUIRE(loading > 0.0f && loading < 1e30f, USBF_EINVAL, "loading must be finite and > 0");
   const int blocks = (n_pix + kMvPixPerBlock - 1) / kMvPixPerBlock;
-  hipLaunchKernelGGL(mv_kernel, dim3(blocks), dim3(64), 0, stream, x, n_pix, n_el, loading, w_full, y);
+  if (n_avg == 1)
+    hipLaunchKernelGGL(mv_kernel<false>, dim3(blocks), dim3(64), 0, stream, x, n_pix, 1, n_el, loading, w_full, y);
+  else
+    hipLaunchKernelGGL(mv_kernel<true>, dim3(blocks), dim3(64), 0, stream, x, n_pix, int(n_avg), n_el, loading, w_full,
+                       y);
   return check_launch("mv_kernel");
+}
+
+extern "C" int usbf_mv_weights(const float* x, int32_t n_pix, int32_t n_el, int32_t subap, float loading,
+                               float* w_full, float* y, hipStream_t stream) {
+  return mv_launch(x, n_pix, 1, n_el, subap, loading, w_full, y, stream);
+}
+
+extern "C" int usbf_mv_weights_averaged(const float* x, int32_t n_pix, int32_t n_avg, int32_t n_el, int32_t subap,
+                                        float loading, float* w_full, float* y, hipStream_t stream) {
+  return mv_launch(x, n_pix, n_avg, n_el, subap, loading, w_full, y, stream);
 }

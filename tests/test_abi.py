@@ -116,6 +116,18 @@ def test_combine_lines_rejects(u):
     assert L.usbf_combine_lines(FAKE, 1, 4, 10, FAKE, FAKE, 2, 3, FAKE + 8, None) == -1
 
 
+def test_mv_rejects(u):
+    L = u.lib()
+    assert L.usbf_mv_weights(None, 4, 128, 32, 1e-2, FAKE, FAKE, None) == -1
+    assert L.usbf_mv_weights(FAKE, 4, 128, 16, 1e-2, FAKE, FAKE, None) == -3       # subaperture 32 only
+    assert L.usbf_mv_weights(FAKE, 4, 300, 32, 1e-2, FAKE, FAKE, None) == -3
+    assert L.usbf_mv_weights(FAKE, 4, 128, 32, 0.0, FAKE, FAKE, None) == -1
+    assert L.usbf_mv_weights_averaged(FAKE, 4, 2, 128, 32, 1e-2, FAKE, FAKE, None) == -1   # even
+    assert L.usbf_mv_weights_averaged(FAKE, 4, 0, 128, 32, 1e-2, FAKE, FAKE, None) == -1
+    assert L.usbf_mv_weights_averaged(FAKE, 4, 257, 128, 32, 1e-2, FAKE, FAKE, None) == -1
+    assert L.usbf_mv_weights_averaged(FAKE, 4, 5, 128, 32, 1e-2, None, None, None) == -1
+
+
 def test_envelope_and_log_reject(u):
     L = u.lib()
     assert L.usbf_envelope(FAKE, 4, 4, FAKE, None, None) == -3            # too short

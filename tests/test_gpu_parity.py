@@ -351,3 +351,33 @@ def test_mv_closed_forms_on_gpu(usbf):
     K = 97
     count = np.array([min(e, 31) - max(0, e - K + 1) + 1 for e in range(M)])
     np.testing.assert_allclose(wf.cpu().numpy(), np.broadcast_to(count / (K * 32), (3, M)), atol=1e-6)
+
+
+def test_mv_weights_averaged_match_oracle(usbf):
+    """Covariance averaged over 5 neighbouring depths (clamped at the line ends) of gathered
+    samples, against the float64 oracle on the same binary32 inputs, at the tolerances of the
+    single-depth estimator; one depth equals the single-depth entry point bit for bit."""
+    from oracle import mv
+    g = synth.config_multiline_2d()
+    rf = sim(g, 3300)
+    dg = usbf.DeviceGeometry(g)
+    rng = np.random.default_rng(2)
+    m = 1500
+    pix = np.stack([np.zeros(m, int), rng.integers(0, g.n_lines, m), rng.integers(0, g.n_depth, m)], 1)
+    pix[:3, 2] = [0, 1, g.n_depth - 1]  # the clamped ends of a line
+    p5 = usbf.depth_neighbours(torch.as_tensor(pix, dtype=torch.int32).cuda(), 5, g.n_depth)
+    x = usbf.delay_gather(rf, dg, p5).view(m, 5, g.n_el)
+    wf, y = usbf.mv_weights_averaged(x, 32, 1e-2)
+    xr = x.cpu().numpy().astype(np.float64)
+    wf_ref, y_ref, _ = mv.mv_weights_averaged(xr, 32, 1e-2)
+    wf = wf.cpu().numpy()
+    rel = np.linalg.norm(wf - wf_ref, axis=1) / np.linalg.norm(wf_ref, axis=1)
+    assert np.median(rel) < 1e-3 and rel.max() < 1e-2
+    assert np.abs(y.cpu().numpy() - y_ref).max() <= 1e-3 * np.abs(y_ref).max()
+    np.testing.assert_allclose(wf.sum(1), 1.0, atol=1e-5)
+    # the middle row is the pixel itself, and one row is the single-depth estimator exactly
+    x1 = usbf.delay_gather(rf, dg, torch.as_tensor(pix, dtype=torch.int32).cuda())
+    assert torch.equal(x[:, 2].contiguous(), x1)
+    a, ya = usbf.mv_weights_averaged(x1.view(m, 1, g.n_el).contiguous(), 32, 1e-2)
+    b, yb = usbf.mv_weights(x1, 32, 1e-2)
+    assert torch.equal(a, b) and torch.equal(ya, yb)
