@@ -182,6 +182,9 @@ def main():
     ap.add_argument("--envelope", default="hilbert", choices=["hilbert", "iq"],
                     help="envelope detector: analytic signal (default) or IQ demodulation with three "
                          "compounded bands at 0.8, 1.0, 1.2 f0 (63 taps, bandwidth 0.4 f0)")
+    ap.add_argument("--streams", type=int, default=1, choices=[1, 2, 3],
+                    help="streams that consecutive batches alternate between (detection and scan "
+                         "conversion of one batch overlap the next batch's delay-and-sum)")
     ap.add_argument("--apod-sets", type=int, default=1, choices=[1, 2, 4],
                     help="beamform with this many apodization sets in one pass (f-number 1.0 Hann, "
                          "1.75 rect, 1.5 Hann, 2.5 rect) and take every set through the pipeline")
@@ -221,64 +224,85 @@ def main():
     set_fn, set_win = [1.0, 1.75, 1.5, 2.5][:n_sets], [1, 0, 1, 0][:n_sets]
     # with several apodization sets every set is an image of its own: S x F images per step
     FI = F * n_sets
-    ws = u.BmodeWorkspace(dg, FI)
-    lines = ws.lines(dg)
     n_angles = getattr(g, "n_angles", 0)
     overlap = hasattr(g, "combine_src")
-    # plane waves: the lines of every angle are compounded into the image lines first;
-    # overlapping layouts: the output lines are interpolated from the transmits' beams
-    if n_angles:
-        det = torch.empty((FI, g.n_lines // n_angles, g.n_depth), dtype=torch.float32, device=dev)
-    elif overlap:
-        det = torch.empty((FI, g.n_out_lines, g.n_depth), dtype=torch.float32, device=dev)
+    if overlap:
         c_src = torch.as_tensor(g.combine_src, device=dev)
         c_w = torch.as_tensor(g.combine_w, device=dev)
-    else:
-        det = lines
-    row_max = torch.empty(det.shape[:2], dtype=torch.float32, device=dev)
-    img = torch.empty((FI, *dg.scan_shape), dtype=torch.float32, device=dev)
-
-    iq_env = torch.empty_like(det) if args.envelope == "iq" else None
     line_fs = float(g.fs) / g.depth_step
     iq_bands = [0.8 * g.f0, g.f0, 1.2 * g.f0]
 
-    def step(ev=None):
-        if ev is not None:
-            ev[0].record()
-        if n_sets > 1:
-            u.beamform_sets(rf, dg, set_fn, set_win, out=lines.view(n_sets, F, *lines.shape[1:]))
-        else:
-            u.beamform(rf, dg, out=lines)
-        if ev is not None:
-            ev[1].record()
+    def buffers():
+        b = {"lines": torch.empty((FI, g.n_lines, g.n_depth), dtype=torch.float32, device=dev)}
+        # plane waves: the lines of every angle are compounded into the image lines first;
+        # overlapping layouts: the output lines are interpolated from the transmits' beams
         if n_angles:
-            u.compound(lines, n_angles, out=det)
+            b["det"] = torch.empty((FI, g.n_lines // n_angles, g.n_depth), dtype=torch.float32, device=dev)
         elif overlap:
-            u.combine_lines(lines, c_src, c_w, out=det)
-        if iq_env is not None:
-            u.envelope_iq(det, line_fs, iq_bands, 0.4 * g.f0, 63, out=iq_env, row_max=row_max)
+            b["det"] = torch.empty((FI, g.n_out_lines, g.n_depth), dtype=torch.float32, device=dev)
         else:
-            u.envelope(det, out=det, row_max=row_max)
-        if ev is not None:
-            ev[2].record()
-        u.log_scan_convert(iq_env if iq_env is not None else det, dg, 50.0, row_max=row_max, out=img)
-        if ev is not None:
-            ev[3].record()
+            b["det"] = b["lines"]
+        b["row_max"] = torch.empty(b["det"].shape[:2], dtype=torch.float32, device=dev)
+        b["img"] = torch.empty((FI, *dg.scan_shape), dtype=torch.float32, device=dev)
+        b["iq_env"] = torch.empty_like(b["det"]) if args.envelope == "iq" else None
+        return b
 
-    for _ in range(args.warmup):
-        step()
+    # Consecutive batches alternate between n_streams streams, each with its own buffers: the
+    # delay-and-sum launches stay in order (each waits for the previous one), and a batch's
+    # detection and scan conversion overlap the next batch's delay-and-sum.
+    n_streams = args.streams
+    streams = [torch.cuda.current_stream(dev)] + [torch.cuda.Stream(dev) for _ in range(n_streams - 1)]
+    bufs = [buffers() for _ in range(n_streams)]
+    das_done = [torch.cuda.Event() for _ in range(n_streams)]
+    last = [None]
+
+    def step(k, ev=None):
+        si = k % n_streams
+        b = bufs[si]
+        with torch.cuda.stream(streams[si]):
+            if last[0] is not None:
+                streams[si].wait_event(das_done[last[0]])
+            if ev is not None:
+                ev[0].record()
+            if n_sets > 1:
+                u.beamform_sets(rf, dg, set_fn, set_win, out=b["lines"].view(n_sets, F, *b["lines"].shape[1:]))
+            else:
+                u.beamform(rf, dg, out=b["lines"])
+            das_done[si].record()
+            last[0] = si
+            if ev is not None:
+                ev[1].record()
+            if n_angles:
+                u.compound(b["lines"], n_angles, out=b["det"])
+            elif overlap:
+                u.combine_lines(b["lines"], c_src, c_w, out=b["det"])
+            if b["iq_env"] is not None:
+                u.envelope_iq(b["det"], line_fs, iq_bands, 0.4 * g.f0, 63, out=b["iq_env"], row_max=b["row_max"])
+            else:
+                u.envelope(b["det"], out=b["det"], row_max=b["row_max"])
+            if ev is not None:
+                ev[2].record()
+            u.log_scan_convert(b["iq_env"] if b["iq_env"] is not None else b["det"], dg, 50.0,
+                               row_max=b["row_max"], out=b["img"])
+            if ev is not None:
+                ev[3].record()
+
+    for k in range(args.warmup):
+        step(k)
     torch.cuda.synchronize()
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        step(evs[k])
+        step(k, evs[k])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     das_ms = np.array([e[0].elapsed_time(e[1]) for e in evs])
     env_ms = np.array([e[1].elapsed_time(e[2]) for e in evs])
     scan_ms = np.array([e[2].elapsed_time(e[3]) for e in evs])
     step_ms = wall * 1e3 / args.steps
+    img = bufs[(args.steps - 1) % n_streams]["img"]
+    iq_env = bufs[0]["iq_env"]
 
     # the whole-pipeline entry point gives the same image (it has the analytic-signal envelope
     # and no compounding)
@@ -307,6 +331,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": desc, "frames_per_batch": F, "envelope": args.envelope, "apod_sets": n_sets,
+                   "streams": n_streams,
                    "unique_frames": min(args.unique_frames, F), "dyn_range_db": 50},
         "frames_per_s": FI / (step_ms * 1e-3),
         "stage_ms": {"das": float(das_ms.mean()),
