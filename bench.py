@@ -145,8 +145,9 @@ def cpu_baseline(g, rf_host, budget_s):
     import oracle
     t0 = time.perf_counter()
     n = 0
-    while n < rf_host.shape[0]:
-        y = oracle.das(g, rf_host[n:n + 1])
+    while True:  # whole frames, cycling through the batch, until the budget is spent
+        i = n % rf_host.shape[0]
+        y = oracle.das(g, rf_host[i:i + 1])
         n_angles = getattr(g, "n_angles", 0)
         if n_angles:  # coherent compounding of the plane-wave lines
             y = y.reshape(1, n_angles, g.n_lines // n_angles, g.n_depth).mean(axis=1)
@@ -163,7 +164,7 @@ def cpu_baseline(g, rf_host, budget_s):
     pcs = n * beams(g) * g.n_depth * g.n_el
     return {"value": pcs / dt, "unit": "pixel·channel samples/s", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": f"{n} frame(s) of the batch through the float64 oracle (DAS"
+            "sample": f"{n} frame(s) of the batch, cycled, through the float64 oracle (DAS"
                       f"{' + compounding' if getattr(g, 'n_angles', 0) else ''}"
                       f"{' + line interpolation' if hasattr(g, 'combine_src') else ''} + envelope + log + scan "
                       f"conversion), {dt:.1f} s"}
