@@ -188,6 +188,9 @@ def main():
     ap.add_argument("--streams", type=int, default=1, choices=[1, 2, 3],
                     help="streams that consecutive batches alternate between (detection and scan "
                          "conversion of one batch overlap the next batch's delay-and-sum)")
+    ap.add_argument("--unordered", action="store_true",
+                    help="with several streams, let the delay-and-sum launches of consecutive batches "
+                         "overlap too (their event-timed durations then include each other)")
     ap.add_argument("--apod-sets", type=int, default=1, choices=[1, 2, 4],
                     help="beamform with this many apodization sets in one pass (f-number 1.0 Hann, "
                          "1.75 rect, 1.5 Hann, 2.5 rect) and take every set through the pipeline")
@@ -263,7 +266,7 @@ def main():
         si = k % n_streams
         b = bufs[si]
         with torch.cuda.stream(streams[si]):
-            if last[0] is not None:
+            if last[0] is not None and not args.unordered:
                 streams[si].wait_event(das_done[last[0]])
             if ev is not None:
                 ev[0].record()
@@ -334,7 +337,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": desc, "frames_per_batch": F, "envelope": args.envelope, "apod_sets": n_sets,
-                   "streams": n_streams,
+                   "streams": n_streams, "unordered_das": bool(args.unordered and n_streams > 1),
                    "unique_frames": min(args.unique_frames, F), "dyn_range_db": 50},
         "frames_per_s": FI / (step_ms * 1e-3),
         "stage_ms": {"das": float(das_ms.mean()),

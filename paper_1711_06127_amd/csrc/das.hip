@@ -577,16 +577,29 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
   }
 }
 
-// One workgroup per tile; workgroup ids are remapped so that consecutive depth tiles of a line
-// group run on the same XCD (they share the edges of their channel-data windows in L2).
+// One workgroup per tile.  Workgroup ids are remapped so that the depth tiles of a line group
+// run one after another on the same XCD (they share the edges of their channel-data windows in
+// L2), and the line groups are dealt to the XCDs round-robin (workgroup id i runs on XCD i % 8):
+// the aperture of lines near the ends of the array is cut by the array's edge, so contiguous
+// blocks of groups would leave the XCDs holding the edges idle at the end while the others
+// still work on the centre.
 template <bool VEC, int G, int FB, int FS, bool SETS>
 __global__ __launch_bounds__(kDasThreads) void das_tile_kernel(const int16_t* __restrict__ rf, int frame0,
                                                                int n_blocks, DasArgs a, TileArgs ta,
                                                                float* __restrict__ out) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  const uint32_t bid = xcd_swizzle(blockIdx.x, gridDim.x);
-  das_tile<VEC, G, FB, FS, SETS>(rf, frame0, n_blocks, a, ta, out, lds_raw, int(bid / ta.n_dtiles),
-                           int(bid % ta.n_dtiles));
+  const uint32_t n_groups = gridDim.x / uint32_t(ta.n_dtiles);
+  int group, dt;
+  if (n_groups % kNumXcd == 0) {
+    const uint32_t xcd = blockIdx.x % kNumXcd, idx = blockIdx.x / kNumXcd;
+    group = int((idx / uint32_t(ta.n_dtiles)) * kNumXcd + xcd);
+    dt = int(idx % uint32_t(ta.n_dtiles));
+  } else {
+    const uint32_t bid = xcd_swizzle(blockIdx.x, gridDim.x);
+    group = int(bid / ta.n_dtiles);
+    dt = int(bid % ta.n_dtiles);
+  }
+  das_tile<VEC, G, FB, FS, SETS>(rf, frame0, n_blocks, a, ta, out, lds_raw, group, dt);
 }
 
 // Persistent delay-and-sum over a table of items of different sizes (one frame each): every
