@@ -183,23 +183,58 @@ __device__ inline float cell_value_log(const float* __restrict__ L, const Cell& 
   }
 }
 
-// One lane per output pixel; the cell is computed once and applied to every frame.
+// One lane per output pixel; the cell is computed once and applied to every frame.  Frames go
+// in groups of kScanFrames whose corner reads are all issued before any is used (the reads
+// are gathers from L2; one frame at a time would leave the lane waiting on each in turn).
+// A workgroup covers a 16 x 16 block of pixels (x by rows, a row being one (y, z) of the
+// grid), each wave an 8 x 8 quarter of it: neighbouring output rows read neighbouring depths
+// of the same lines, so a wave's corner reads fall on a few line segments instead of one
+// line per lane, as a row-major wave would have them.
+constexpr int kScanFrames = 4;
+constexpr int kScanTile = 16;
+
+__device__ inline int64_t scan_pixel(const ScanArgs& a, bool& ok) {
+  const int64_t rows = a.grid / a.nx;
+  const int64_t tiles_x = (a.nx + kScanTile - 1) / kScanTile;
+  const int64_t b = blockIdx.x;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int64_t x = (b % tiles_x) * kScanTile + (w & 1) * 8 + (l & 7);
+  const int64_t r = (b / tiles_x) * kScanTile + (w >> 1) * 8 + (l >> 3);
+  ok = x < a.nx && r < rows;
+  return r * a.nx + x;
+}
+
+__host__ inline int64_t scan_blocks(const ScanArgs& a) {
+  const int64_t rows = a.grid / a.nx;
+  return ((a.nx + kScanTile - 1) / kScanTile) * ((rows + kScanTile - 1) / kScanTile);
+}
+
 template <bool LOG>
 __global__ __launch_bounds__(kScanThreads) void scan_kernel(const float* __restrict__ in, int n_frames, ScanArgs a,
                                                             const float* __restrict__ frame_ref, float dyn_range_db,
                                                             float* __restrict__ out) {
-  const int64_t p = int64_t(blockIdx.x) * kScanThreads + threadIdx.x;
-  if (p >= a.grid) return;
+  bool ok;
+  const int64_t p = scan_pixel(a, ok);
+  if (!ok) return;
   const Cell c = scan_cell(a, p);
-  for (int f = 0; f < n_frames; ++f) {
-    float v = a.fill;
-    if (c.base >= 0) {
-      LogMap m{};
-      if constexpr (LOG) m = log_map(dyn_range_db, frame_ref[f]);
-      v = cell_value_log<LOG>(in + int64_t(f) * a.frame_in, c, a.n_depth, a.kind, m);
-    }
-    out[int64_t(f) * a.grid + p] = v;
+  if (c.base < 0) {
+    for (int f = 0; f < n_frames; ++f) out[int64_t(f) * a.grid + p] = a.fill;
+    return;
   }
+  auto frame_value = [&](int f) {
+    LogMap m{};
+    if constexpr (LOG) m = log_map(dyn_range_db, frame_ref[f]);
+    return cell_value_log<LOG>(in + int64_t(f) * a.frame_in, c, a.n_depth, a.kind, m);
+  };
+  int f = 0;
+  for (; f + kScanFrames <= n_frames; f += kScanFrames) {
+    float v[kScanFrames];
+#pragma unroll
+    for (int u = 0; u < kScanFrames; ++u) v[u] = frame_value(f + u);
+#pragma unroll
+    for (int u = 0; u < kScanFrames; ++u) out[int64_t(f + u) * a.grid + p] = v[u];
+  }
+  for (; f < n_frames; ++f) out[int64_t(f) * a.grid + p] = frame_value(f);
 }
 
 __global__ void scan_index_kernel(ScanArgs a, int32_t* __restrict__ base) {
@@ -249,7 +284,10 @@ int frame_max_enqueue(const float* x, int n_frames, int64_t frame_len, float* ws
 
 int scan_enqueue(const float* in, int n_frames, const ScanArgs& a, const float* frame_ref, float dr_db, bool log,
                  float* out, hipStream_t s) {
-  dim3 grid(unsigned((a.grid + kScanThreads - 1) / kScanThreads));
+  static_assert(kScanThreads == kScanTile * kScanTile, "one lane per pixel of a tile");
+  const int64_t blocks = scan_blocks(a);
+  if (blocks > 0x7fffffff) return fail(USBF_EUNSUPPORTED, "scan grid too large");
+  const dim3 grid(static_cast<unsigned>(blocks));
   if (log)
     hipLaunchKernelGGL(scan_kernel<true>, grid, dim3(kScanThreads), 0, s, in, n_frames, a, frame_ref, dr_db, out);
   else
