@@ -274,7 +274,25 @@ __global__ void log_kernel(const float* env, int64_t frame_len, const float* __r
     o[i] = log_apply(m, e[i]);
 }
 
+// Max of each frame by one workgroup per frame, written directly (frames of up to 4096 values,
+// e.g. the row maxima of a frame): no zero fill and no atomics.
+__global__ __launch_bounds__(256) void frame_max_direct_kernel(const float* __restrict__ x, int64_t frame_len,
+                                                               float* __restrict__ fmax) {
+  __shared__ float red[4];
+  const float* p = x + int64_t(blockIdx.x) * frame_len;
+  float m = 0.0f;
+  for (int64_t i = threadIdx.x; i < frame_len; i += blockDim.x) m = fmaxf(m, p[i]);
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) fmax[blockIdx.x] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+}
+
 int frame_max_enqueue(const float* x, int n_frames, int64_t frame_len, float* ws, hipStream_t s) {
+  if (frame_len <= 4096) {
+    hipLaunchKernelGGL(frame_max_direct_kernel, dim3(n_frames), dim3(256), 0, s, x, frame_len, ws);
+    return check_launch("frame_max_direct_kernel");
+  }
   hipLaunchKernelGGL(fill_kernel, dim3((n_frames + 255) / 256), dim3(256), 0, s, ws, int64_t(n_frames), 0.0f);
   int chunks = int(std::min<int64_t>((frame_len + 4095) / 4096, 256));
   hipLaunchKernelGGL(frame_max_kernel, dim3(chunks, n_frames), dim3(256), 0, s, x, frame_len, chunks,
