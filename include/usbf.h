@@ -296,13 +296,27 @@ int usbf_mv_weights(const float* x, int32_t n_pix, int32_t n_el, int32_t subap, 
                     float* w_full, float* y, hipStream_t stream);
 
 /*
+ * Delayed channel samples at neighbouring depths, the input of temporally averaged minimum
+ * variance (usbf_mv_weights_averaged): for each listed pixel (frame f, line l, depth j) the
+ * samples of usbf_delay_gather at the n_avg depths j - n_avg/2 .. j + n_avg/2 of line l,
+ * each clamped to 0 .. n_depth - 1 (at the ends of a line the edge depth repeats).
+ *   pix  int32 [n_pix][3], as usbf_delay_gather (a listed pixel out of range gives n_avg rows
+ *        of zeros);  n_avg odd, 1..255
+ *   x    float [n_pix][n_avg][n_el]: row t of pixel p is depth j + t - n_avg/2 (clamped)
+ * n_avg = 1 is usbf_delay_gather.  Same status codes as usbf_delay_gather, plus USBF_EINVAL
+ * for an even or out-of-range n_avg.
+ */
+int usbf_delay_gather_depths(const int16_t* rf, int32_t n_frames, const usbf_geometry* geom, const usbf_rx* rx,
+                             const int32_t* pix, int32_t n_pix, int32_t n_avg, float* x, hipStream_t stream);
+
+/*
  * Minimum variance with temporal averaging (the same estimator, not in the paper): the
  * covariance also averages over n_avg neighbouring depth samples of the pixel's line,
  *   R = (1/(n_avg K)) sum_t sum_l x_{t,l} x_{t,l}^T   (binary32, rows in order t = 0 ..),
  * and the weights apply to the middle row, y = w_full^T x_{n_avg/2}.  Loading, solve and
  * expansion as usbf_mv_weights(), which is the case n_avg = 1 (bit for bit).
  *   x  float [n_pix][n_avg][n_el]: for each pixel the delayed samples at n_avg consecutive
- *      depths (how the edges of a line are handled is the caller's choice);
+ *      depths, as usbf_delay_gather_depths() writes them (clamped at the ends of a line);
  *   n_avg odd, 1..255; other arguments as usbf_mv_weights().
  */
 int usbf_mv_weights_averaged(const float* x, int32_t n_pix, int32_t n_avg, int32_t n_el, int32_t subap,

@@ -71,6 +71,7 @@ _SIGS = {
     "usbf_delay_index_map": (I32, [P, P, P, P, P, P]),
     "usbf_scan_index_map": (I32, [P, P, P]),
     "usbf_delay_gather": (I32, [P, I32, P, P, P, I32, P, P]),
+    "usbf_delay_gather_depths": (I32, [P, I32, P, P, P, I32, I32, P, P]),
     "usbf_mv_weights": (I32, [P, I32, I32, I32, F32, P, P, P]),
     "usbf_mv_weights_averaged": (I32, [P, I32, I32, I32, I32, F32, P, P, P]),
     "usbf_apodnet_state_bytes": (ctypes.c_size_t, []),
@@ -389,17 +390,28 @@ def scan_index_map(dg: DeviceGeometry) -> torch.Tensor:
     return base
 
 
-def delay_gather(rf: torch.Tensor, dg: DeviceGeometry, pix: torch.Tensor, out: torch.Tensor | None = None):
-    """Delayed channel samples x [n_pix, n_el] for pixels pix int32 [n_pix, 3] (frame, line, depth)."""
+def delay_gather(rf: torch.Tensor, dg: DeviceGeometry, pix: torch.Tensor, out: torch.Tensor | None = None,
+                 n_avg: int = 1):
+    """Delayed channel samples for pixels pix int32 [n_pix, 3] (frame, line, depth): x [n_pix, n_el],
+    or with n_avg > 1 (odd) x [n_pix, n_avg, n_el], the samples at the n_avg depths centred on
+    each pixel (clamped to the line by the library)."""
     _need_cuda(rf, "rf", torch.int16)
     if rf.dim() == 3:
         rf = rf.unsqueeze(0)
     _need_cuda(pix, "pix", torch.int32)
     n = pix.shape[0]
+    shape = (n, dg.n_el) if n_avg == 1 else (n, n_avg, dg.n_el)
     if out is None:
-        out = torch.empty((n, dg.n_el), dtype=torch.float32, device=rf.device)
-    _check(lib().usbf_delay_gather(_ptr(rf), rf.shape[0], ctypes.byref(dg.geom), ctypes.byref(dg.rx), _ptr(pix), n,
-                                   _ptr(out), _stream(rf.device)))
+        out = torch.empty(shape, dtype=torch.float32, device=rf.device)
+    _need_cuda(out, "out", torch.float32)
+    if tuple(out.shape) != shape:
+        raise ValueError(f"out must be {shape}")
+    if n_avg == 1:
+        _check(lib().usbf_delay_gather(_ptr(rf), rf.shape[0], ctypes.byref(dg.geom), ctypes.byref(dg.rx), _ptr(pix),
+                                       n, _ptr(out), _stream(rf.device)))
+    else:
+        _check(lib().usbf_delay_gather_depths(_ptr(rf), rf.shape[0], ctypes.byref(dg.geom), ctypes.byref(dg.rx),
+                                              _ptr(pix), n, n_avg, _ptr(out), _stream(rf.device)))
     return out
 
 
@@ -422,15 +434,6 @@ def mv_weights_averaged(x: torch.Tensor, subap: int = 32, loading: float = 1e-2,
     y = torch.empty(n, dtype=torch.float32, device=x.device)
     _check(lib().usbf_mv_weights_averaged(_ptr(x), n, t, m, subap, loading, _ptr(wf), _ptr(y), _stream(x.device)))
     return wf, y
-
-
-def depth_neighbours(pix: torch.Tensor, n_avg: int, n_depth: int) -> torch.Tensor:
-    """Pixel list [n, 3] (frame, line, depth) -> [n * n_avg, 3]: for each pixel the n_avg
-    depths centred on it, clamped to the line (the edge sample repeats)."""
-    off = torch.arange(n_avg, device=pix.device, dtype=torch.int32) - n_avg // 2
-    p = pix[:, None, :].repeat(1, n_avg, 1)
-    p[:, :, 2] = (p[:, :, 2] + off[None, :]).clamp(0, n_depth - 1)
-    return p.reshape(-1, 3).contiguous()
 
 
 OP_APODNET_TRAIN = 6

@@ -233,9 +233,11 @@ __host__ __device__ constexpr int last_src(int cur) {
   return (NS * radix_at<N, NS>() == N) ? cur : last_src<N, NS * radix_at<N, NS>()>(cur ^ 1);
 }
 
+// in == env is allowed (the pipeline detects in place): every row is read whole before any
+// of it is written, and the prefetched next row is another row, so neither pointer is
+// declared restrict.
 template <int N>
-__global__ __launch_bounds__(kEnvThreads) void envelope_pow2_kernel(const float* __restrict__ in, int64_t n_rows,
-                                                                    float* __restrict__ env,
+__global__ __launch_bounds__(kEnvThreads) void envelope_pow2_kernel(const float* in, int64_t n_rows, float* env,
                                                                     float* __restrict__ row_max) {
   static_assert(N >= 64 && (N & (N - 1)) == 0 && N <= kMaxEnvelopeLength, "power-of-two length");
   extern __shared__ c32 lds[];

@@ -18,20 +18,26 @@ namespace usbf {
 constexpr int kGatherPix = 64;     // pixels per workgroup
 constexpr int kGatherChunk = 128;  // elements per LDS transpose chunk
 
+// Output row q = p * n_avg + t holds listed pixel p's samples at depth j_p + t - n_avg / 2,
+// clamped to the line (n_avg = 1: the pixel itself).
 __global__ __launch_bounds__(256) void gather_kernel(const int16_t* __restrict__ rf, int n_frames, DasArgs a,
-                                                     const int32_t* __restrict__ pix, int n_pix,
+                                                     const int32_t* __restrict__ pix, int n_pix, int n_avg,
                                                      float* __restrict__ x) {
   __shared__ float tile[kGatherPix][kGatherChunk + 1];
   const int pl = threadIdx.x % kGatherPix;
   const int eg = threadIdx.x / kGatherPix;  // 4 element lanes per pixel
-  const int p = blockIdx.x * kGatherPix + pl;
+  const int64_t n_rows = int64_t(n_pix) * n_avg;
+  const int64_t q = int64_t(blockIdx.x) * kGatherPix + pl;
   int f = 0, l = 0, j = 0;
-  bool ok = p < n_pix;
+  bool ok = q < n_rows;
   if (ok) {
+    const int64_t p = q / n_avg;
+    const int t = int(q - p * n_avg);
     f = pix[3 * p];
     l = pix[3 * p + 1];
     j = pix[3 * p + 2];
     ok = f >= 0 && f < n_frames && l >= 0 && l < a.n_lines && j >= 0 && j < a.n_depth;
+    j = min(max(j + t - n_avg / 2, 0), a.n_depth - 1);
   }
   LineGeom L;
   line_geom(a, ok ? l : 0, L);
@@ -62,8 +68,8 @@ __global__ __launch_bounds__(256) void gather_kernel(const int16_t* __restrict__
     // coalesced write-out: consecutive lanes write consecutive elements of one pixel row
     for (int idx = threadIdx.x; idx < kGatherPix * nc; idx += 256) {
       const int pp = idx / nc, k = idx - pp * nc;
-      const int pg = blockIdx.x * kGatherPix + pp;
-      if (pg < n_pix) x[size_t(pg) * a.n_el + c0 + k] = tile[pp][k];
+      const int64_t qg = int64_t(blockIdx.x) * kGatherPix + pp;
+      if (qg < n_rows) x[size_t(qg) * a.n_el + c0 + k] = tile[pp][k];
     }
     __syncthreads();
   }
@@ -224,16 +230,30 @@ __global__ __launch_bounds__(64) void mv_kernel(const float* __restrict__ xin, i
 
 using namespace usbf;
 
-extern "C" int usbf_delay_gather(const int16_t* rf, int32_t n_frames, const usbf_geometry* geom, const usbf_rx* rx,
-                                 const int32_t* pix, int32_t n_pix, float* x, hipStream_t stream) {
+static int gather_launch(const int16_t* rf, int32_t n_frames, const usbf_geometry* geom, const usbf_rx* rx,
+                         const int32_t* pix, int32_t n_pix, int32_t n_avg, float* x, hipStream_t stream) {
   DasArgs a;
   int st = make_das_args(geom, rx, &a);
   if (st) return st;
   USBF_REQUIRE(rf && pix && x, USBF_EINVAL, "null rf, pix or x");
   USBF_REQUIRE(n_frames >= 1 && n_pix >= 1, USBF_EINVAL, "n_frames and n_pix must be >= 1");
-  const int blocks = (n_pix + kGatherPix - 1) / kGatherPix;
-  hipLaunchKernelGGL(gather_kernel, dim3(blocks), dim3(256), 0, stream, rf, n_frames, a, pix, n_pix, x);
+  USBF_REQUIRE(n_avg >= 1 && n_avg <= 255 && n_avg % 2 == 1, USBF_EINVAL, "n_avg %d: must be odd in 1..255", n_avg);
+  const int64_t blocks = (int64_t(n_pix) * n_avg + kGatherPix - 1) / kGatherPix;
+  USBF_REQUIRE(blocks <= 0x7fffffff, USBF_EUNSUPPORTED, "too many gathered rows");
+  hipLaunchKernelGGL(gather_kernel, dim3(unsigned(blocks)), dim3(256), 0, stream, rf, n_frames, a, pix, n_pix,
+                     int(n_avg), x);
   return check_launch("gather_kernel");
+}
+
+extern "C" int usbf_delay_gather(const int16_t* rf, int32_t n_frames, const usbf_geometry* geom, const usbf_rx* rx,
+                                 const int32_t* pix, int32_t n_pix, float* x, hipStream_t stream) {
+  return gather_launch(rf, n_frames, geom, rx, pix, n_pix, 1, x, stream);
+}
+
+extern "C" int usbf_delay_gather_depths(const int16_t* rf, int32_t n_frames, const usbf_geometry* geom,
+                                        const usbf_rx* rx, const int32_t* pix, int32_t n_pix, int32_t n_avg, float* x,
+                                        hipStream_t stream) {
+  return gather_launch(rf, n_frames, geom, rx, pix, n_pix, n_avg, x, stream);
 }
 
 static int mv_launch(const float* x, int32_t n_pix, int32_t n_avg, int32_t n_el, int32_t subap, float loading,

@@ -259,3 +259,17 @@ def test_lines_per_tx_hint(u):
     assert h(np.array([-1, -1, -1, -1, 0, 0, 0, 0])) == 4
     assert h(np.array([0, -1, 0, -1, 1, 1, 1, -1])) == 4
     assert h(np.array([-1, 0, 0, 0, 1, 1, 1, 1])) == 1
+
+
+def test_delay_gather_rejects(u):
+    L = u.lib()
+    g, r = geom(u), rx(u)
+    bg, br = ctypes.byref(g), ctypes.byref(r)
+    assert L.usbf_delay_gather(None, 1, bg, br, FAKE, 4, FAKE, None) == -1
+    assert L.usbf_delay_gather(FAKE, 0, bg, br, FAKE, 4, FAKE, None) == -1
+    assert L.usbf_delay_gather(FAKE, 1, bg, br, FAKE, 0, FAKE, None) == -1
+    assert L.usbf_delay_gather_depths(FAKE, 1, bg, br, FAKE, 4, 4, FAKE, None) == -1     # even
+    assert L.usbf_delay_gather_depths(FAKE, 1, bg, br, FAKE, 4, 0, FAKE, None) == -1
+    assert L.usbf_delay_gather_depths(FAKE, 1, bg, br, FAKE, 4, 257, FAKE, None) == -1
+    assert L.usbf_delay_gather_depths(FAKE, 1, bg, br, None, 4, 5, FAKE, None) == -1
+    assert L.usbf_delay_gather_depths(FAKE, 1, bg, br, FAKE, 4, 5, None, None) == -1

@@ -198,6 +198,21 @@ def test_envelope_matches_oracle(usbf, n):
     assert np.array_equal(rm.cpu().numpy(), env.cpu().numpy().max(1))
 
 
+@pytest.mark.parametrize("n", [256, 2048, 1000])
+def test_envelope_in_place(usbf, n):
+    """The pipeline detects in place (output buffer = input buffer); enough rows that every
+    workgroup of the resident grid prefetches a next row while it writes the current one."""
+    rng = np.random.default_rng(n + 1)
+    x = rng.standard_normal((4096, n)).astype(np.float32)
+    buf = torch.as_tensor(x).cuda()
+    sep = usbf.envelope(buf.clone())
+    env, rm = usbf.envelope(buf, out=buf, row_max=True)
+    assert env.data_ptr() == buf.data_ptr()
+    assert torch.equal(env, sep)
+    assert rel_err(env.cpu().numpy(), oracle.envelope(x.astype(np.float64))) <= TOL
+    assert np.array_equal(rm.cpu().numpy(), env.cpu().numpy().max(1))
+
+
 def test_envelope_in_place(usbf):
     x = torch.randn(16, 1024, device="cuda")
     ref = usbf.envelope(x.clone())
@@ -379,8 +394,13 @@ def test_mv_weights_averaged_match_oracle(usbf):
     m = 1500
     pix = np.stack([np.zeros(m, int), rng.integers(0, g.n_lines, m), rng.integers(0, g.n_depth, m)], 1)
     pix[:3, 2] = [0, 1, g.n_depth - 1]  # the clamped ends of a line
-    p5 = usbf.depth_neighbours(torch.as_tensor(pix, dtype=torch.int32).cuda(), 5, g.n_depth)
-    x = usbf.delay_gather(rf, dg, p5).view(m, 5, g.n_el)
+    x = usbf.delay_gather(rf, dg, torch.as_tensor(pix, dtype=torch.int32).cuda(), n_avg=5)
+    assert x.shape == (m, 5, g.n_el)
+    # the library's neighbour rows against the oracle's gather at the clamped depths
+    nb = np.repeat(pix[:, None, :], 5, axis=1)
+    nb[:, :, 2] = np.clip(nb[:, :, 2] + np.arange(-2, 3)[None, :], 0, g.n_depth - 1)
+    ref_x = oracle.delay_gather(g, rf.cpu().numpy(), nb.reshape(-1, 3)).reshape(m, 5, g.n_el)
+    assert rel_err(x.cpu().numpy(), ref_x) <= TOL
     wf, y = usbf.mv_weights_averaged(x, 32, 1e-2)
     xr = x.cpu().numpy().astype(np.float64)
     wf_ref, y_ref, _ = mv.mv_weights_averaged(xr, 32, 1e-2)
