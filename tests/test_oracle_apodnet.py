@@ -98,3 +98,65 @@ def test_fallback_replaces_non_finite_weights():
     w[1, 2] = np.nan
     y = an.apply_weights(w, x, fallback=np.array([9.0, 7.0, 5.0]))
     np.testing.assert_allclose(y, [1.0, 7.0, 1.0])
+
+
+def test_adam_bias_corrections_give_the_learning_rate_for_a_constant_gradient():
+    """With the same gradient at every step the bias-corrected moments equal g and g^2 exactly,
+    so every step moves each weight by lr * g / (|g| + eps): a missing or wrong correction of
+    either moment changes the step size after the first step."""
+    p = {"a": np.array([1.0, -2.0, 0.5, 3.0], np.float32)}
+    g = {"a": np.array([0.3, -1e-3, 2.0, -40.0])}
+    opt = an.Adam(p, lr=1e-3)
+    cur = p
+    for t in range(1, 6):
+        nxt = opt.step(cur, g)
+        step = nxt["a"].astype(np.float64) - cur["a"].astype(np.float64)
+        np.testing.assert_allclose(step, -1e-3 * np.sign(g["a"]), rtol=2e-3)
+        cur = nxt
+
+
+def _bf16_torch(t):
+    return t.to(torch.float32).to(torch.bfloat16).to(torch.float64)
+
+
+def test_bf16_backward_matches_torch_autograd_with_rounding_at_the_same_points():
+    """The bfloat16 network's analytic gradients against torch autograd of the same forward pass:
+    layer inputs and weights rounded with straight-through derivatives, and the gradients that
+    reach each layer's pre-activation (and the output) rounded by hooks.  A rounding that the
+    oracle's backward pass applies at another point, or omits, changes the gradients by about a
+    bfloat16 ulp and fails the comparison."""
+    F = torch.nn.functional
+    rng = np.random.default_rng(8)
+    params = an.init_params(9)
+    for k in ("b1", "b2", "b3"):
+        params[k] = (rng.standard_normal(params[k].shape) * 0.1).astype(np.float32)
+    params["b4"] = np.float32([0.01])
+    x = rng.standard_normal((6, 32)) * 100.0
+    target = rng.standard_normal((6, 32)) * 0.05
+    w_ref, cache = an.forward(params, x, bf=True)
+    g_ref = an.backward(params, cache, w_ref, target)
+
+    def st(t):  # rounding with a straight-through derivative
+        return t + (_bf16_torch(t) - t).detach()
+
+    P = {k: torch.tensor(v.astype(np.float64), requires_grad=True) for k, v in params.items()}
+    xt = torch.tensor(x)
+    xh = xt / torch.sqrt((xt * xt).mean(dim=1, keepdim=True) + 1e-12)
+    a = st(xh)[:, None, :]
+    zs = []
+    for layer in (1, 2, 3):
+        z = F.conv1d(a, st(P[f"W{layer}"]), P[f"b{layer}"], padding=2)
+        z.register_hook(_bf16_torch)
+        zs.append(z)
+        a = st(torch.relu(z))
+    out = F.conv1d(a, st(P["W4"]), P["b4"], padding=2)
+    out.register_hook(_bf16_torch)
+    w = out[:, 0, :]
+    M = w.shape[1]
+    loss = ((M * w - M * torch.tensor(target)) ** 2).mean()
+    loss.backward()
+    np.testing.assert_allclose(w.detach().numpy(), w_ref, rtol=1e-12, atol=1e-15)
+    for k in params:
+        got = P[k].grad.numpy()
+        scale = np.abs(g_ref[k]).max()
+        assert np.abs(got - g_ref[k]).max() <= 1e-10 * scale, k

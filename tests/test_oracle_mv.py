@@ -133,3 +133,99 @@ def test_averaging_over_depth_limits_signal_cancellation():
         _, y, _ = mv.mv_weights_averaged(np.array(xs), L=L, loading=1e-3)
         err[T] = np.median(np.abs(y - np.array(ss)))
     assert err[9] < 0.5 * err[1]
+
+
+# ---- analytic-signal (complex) covariance
+
+def test_complex_estimator_on_real_data_is_the_real_estimator():
+    rng = np.random.default_rng(21)
+    x = rng.standard_normal((6, 128)) * np.linspace(1, 2, 128)
+    wf, y, w = mv.mv_weights(x)
+    wfc, yc, wc = mv.mv_weights_complex(x + 0j)
+    np.testing.assert_allclose(wc, w, rtol=1e-10, atol=1e-13)
+    np.testing.assert_allclose(wfc, wf, rtol=1e-10, atol=1e-13)
+    np.testing.assert_allclose(yc, y, rtol=1e-10, atol=1e-12)
+
+
+def test_complex_weights_ignore_a_common_phase():
+    """z -> z e^{i phi}: R is unchanged, so are the weights, and y turns by the same phase."""
+    rng = np.random.default_rng(22)
+    z = rng.standard_normal((4, 128)) + 1j * rng.standard_normal((4, 128))
+    wf, y, w = mv.mv_weights_complex(z)
+    ph = np.exp(1j * 0.7)
+    wf2, y2, w2 = mv.mv_weights_complex(z * ph)
+    np.testing.assert_allclose(w2, w, rtol=1e-10, atol=1e-13)
+    np.testing.assert_allclose(y2, y * ph, rtol=1e-10, atol=1e-12)
+
+
+def test_complex_coherent_signal_gives_uniform_weights():
+    c = 2.0 - 1.5j
+    wf, y, w = mv.mv_weights_complex(np.full((2, 128), c))
+    np.testing.assert_allclose(w, 1.0 / 32, atol=1e-14)
+    np.testing.assert_allclose(y, c, rtol=1e-12)
+
+
+def test_complex_kkt_hermitian_and_optimality():
+    """A w = lambda 1 with lambda real and positive; R Hermitian positive semidefinite; no
+    perturbation that keeps 1^T w = 1 lowers w^H A w."""
+    rng = np.random.default_rng(23)
+    z = (rng.standard_normal((4, 128)) + 1j * rng.standard_normal((4, 128))) * np.linspace(1, 3, 128)
+    R = mv.covariance_complex(z, 32)
+    np.testing.assert_allclose(R, np.conj(np.transpose(R, (0, 2, 1))), atol=0)
+    assert np.all(np.linalg.eigvalsh(R) > -1e-12)
+    A = mv.loaded(R, 1e-2)
+    wf, y, w = mv.mv_weights_complex(z)
+    np.testing.assert_allclose(w.sum(1), 1.0, atol=1e-12)
+    for p in range(4):
+        Aw = A[p] @ w[p]
+        lam = Aw.mean()
+        assert abs(lam.imag) < 1e-12 * abs(lam) and lam.real > 0
+        np.testing.assert_allclose(Aw, lam, rtol=1e-10)
+        base = np.real(np.conj(w[p]) @ A[p] @ w[p])
+        for _ in range(20):
+            d = rng.standard_normal(32) + 1j * rng.standard_normal(32)
+            d -= d.mean()
+            u = w[p] + 1e-2 * d
+            assert np.real(np.conj(u) @ A[p] @ u) >= base
+
+
+def test_complex_interference_is_nulled():
+    """Broadside complex signal plus a 20x stronger plane-wave interferer with a linear phase
+    ramp across the aperture: the signal passes, the interferer is nulled."""
+    M, L = 128, 32
+    e = np.arange(M)
+    rng = np.random.default_rng(24)
+    n = 64
+    s = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    ph = rng.uniform(0, 2 * np.pi, n)
+    z = s[:, None] + 20.0 * np.exp(1j * (2 * np.pi * 0.11 * e[None, :] + ph[:, None]))
+    wf, y, w = mv.mv_weights_complex(z, L=L, loading=1e-3)
+    y_uniform = (mv.expand(np.full((n, L), 1.0 / L), M) * z).sum(1)
+    err_mv, err_uniform = np.median(np.abs(y - s)), np.median(np.abs(y_uniform - s))
+    assert err_uniform > 0.02
+    assert err_mv < 0.05 * err_uniform
+
+
+def test_analytic_channels_match_scipy_hilbert():
+    import scipy.signal
+    rng = np.random.default_rng(25)
+    rf = rng.integers(-3000, 3000, size=(2, 3, 4, 250)).astype(np.int16)
+    za = mv.analytic_channels(rf)
+    np.testing.assert_allclose(za, scipy.signal.hilbert(rf.astype(np.float64), axis=-1), atol=1e-9)
+    np.testing.assert_allclose(za.real, rf, atol=1e-9)
+
+
+def test_complex_gather_real_part_is_the_real_gather():
+    """The analytic signal's real part is the channel data itself, so the real part of the
+    complex gather equals the (C) delay-gather of the int16 data at the same taps."""
+    import oracle
+    import synth
+    g = synth.config_tiny(n_el=6, n_tx=2, lines_per_tx=3, n_samples=96)
+    rng = np.random.default_rng(26)
+    rf = rng.integers(-3000, 3000, size=(2, g.n_tx, g.n_el, g.n_samples)).astype(np.int16)
+    za = mv.analytic_channels(rf)
+    pix = np.stack([rng.integers(0, 2, 40), rng.integers(0, g.n_lines, 40), rng.integers(0, g.n_depth, 40)], 1)
+    z = mv.delay_gather_complex(g, za, pix)
+    x = oracle.delay_gather(g, rf, pix)
+    np.testing.assert_allclose(z.real, x, atol=1e-9)
+    assert np.abs(z.imag).max() > 0
