@@ -42,7 +42,10 @@ def kernel_hash(paths):
 
 CALIB_BYTES = 1 << 30
 DAS_SOURCES = ["paper_1711_06127_amd/csrc/das.hip", "paper_1711_06127_amd/csrc/das.h",
-               "paper_1711_06127_amd/csrc/tof.h", "paper_1711_06127_amd/csrc/common.h"]
+               "paper_1711_06127_amd/csrc/das_tile.h", "paper_1711_06127_amd/csrc/das_g1.hip",
+               "paper_1711_06127_amd/csrc/das_g2.hip", "paper_1711_06127_amd/csrc/das_g4.hip",
+               "paper_1711_06127_amd/csrc/das_g8.hip", "paper_1711_06127_amd/csrc/tof.h",
+               "paper_1711_06127_amd/csrc/common.h"]
 
 
 def _counter_rows(path, counter):
