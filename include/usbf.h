@@ -266,6 +266,23 @@ int usbf_bmode(const int16_t* rf, int32_t n_frames, const usbf_geometry* geom, c
                const usbf_scan* scan, float dyn_range_db, float* image, void* ws, size_t ws_bytes,
                hipStream_t stream);
 
+/*
+ * usbf_bmode without a workspace argument, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same stages and results as usbf_bmode, with the workspace taken from a buffer the library
+ * holds on each GPU it runs on (USBF_NOALLOC_SCRATCH_BYTES, allocated with the library's code
+ * object and kept until the process ends).  The call itself allocates nothing.
+ *   Requests whose usbf_workspace_bytes(USBF_OP_BMODE, n_frames, n_lines, n_depth) exceeds
+ *   USBF_NOALLOC_SCRATCH_BYTES fail with USBF_EUNSUPPORTED before anything is enqueued (e.g. up
+ *   to 15 frames of 256 lines x 2048 depths, or 8 volumes of 1024 lines x 1000 depths).
+ *   Every call on one GPU shares that GPU's buffer: calls that overlap in time on one GPU
+ *   (several streams or host threads) race and must be serialised by the caller.
+ * Other arguments, limits and status codes as usbf_bmode().
+ */
+#define USBF_NOALLOC_SCRATCH_BYTES (32u << 20)
+int usbf_bmode_noalloc(const int16_t* rf, int32_t n_frames, const usbf_geometry* geom, const usbf_rx* rx,
+                       const usbf_scan* scan, float dyn_range_db, float* image, hipStream_t stream);
+
 /* ---------------------------------------------------------------- adaptive apodization */
 
 /*

@@ -67,6 +67,7 @@ _SIGS = {
     "usbf_scan_convert": (I32, [P, I32, P, P, P]),
     "usbf_log_scan_convert": (I32, [P, P, I32, P, F32, F32, P, P, ctypes.c_size_t, P]),
     "usbf_bmode": (I32, [P, I32, P, P, P, F32, P, P, ctypes.c_size_t, P]),
+    "usbf_bmode_noalloc": (I32, [P, I32, P, P, P, F32, P, P]),
     "usbf_workspace_bytes": (ctypes.c_size_t, [I32, I64, I64, I64]),
     "usbf_delay_index_map": (I32, [P, P, P, P, P, P]),
     "usbf_scan_index_map": (I32, [P, P, P]),

@@ -128,6 +128,16 @@ def test_mv_rejects(u):
     assert L.usbf_mv_weights_averaged(FAKE, 4, 5, 128, 32, 1e-2, None, None, None) == -1
 
 
+def test_bmode_noalloc_rejects_requests_beyond_its_scratch(u):
+    L = u.lib()
+    g, r = geom(u, n_lines=4), rx(u, n_samples=4096, depth_step=2, n_depth=2048)
+    s = scan(u, n_depth=2048)
+    assert L.usbf_workspace_bytes(3, 1100, 4, 2048) > (32 << 20)
+    assert L.usbf_bmode_noalloc(FAKE, 1100, ctypes.byref(g), ctypes.byref(r), ctypes.byref(s), 50.0, FAKE,
+                                None) == -3
+    assert L.usbf_bmode_noalloc(FAKE, 1, ctypes.byref(g), ctypes.byref(r), ctypes.byref(s), -1.0, FAKE, None) == -1
+
+
 def test_envelope_and_log_reject(u):
     L = u.lib()
     assert L.usbf_envelope(FAKE, 4, 4, FAKE, None, None) == -3            # too short
