@@ -74,20 +74,30 @@ def normalise(x: np.ndarray) -> np.ndarray:
     return x / np.sqrt(np.mean(x * x, axis=1, keepdims=True) + 1e-12)
 
 
-def forward(params, x: np.ndarray, bf: bool = True):
-    """Returns (w [P, M], cache).  x: delayed samples [P, M]."""
+def _jittered(v: np.ndarray, jitter, n_terms: int) -> np.ndarray:
+    """v with every entry scaled by (1 + u * 2^-24 * sqrt(n_terms)), u uniform in [-1, 1]: the
+    size of the rounding error a binary32 accumulator adds to a sum of n_terms products in some
+    order.  Used only to measure how often that error moves a bfloat16 rounding (jitter = a
+    numpy Generator); None leaves v unchanged."""
+    if jitter is None:
+        return v
+    return v * (1.0 + jitter.uniform(-1.0, 1.0, v.shape) * 2.0 ** -24 * np.sqrt(n_terms))
+
+
+def forward(params, x: np.ndarray, bf: bool = True, jitter=None):
+    """Returns (w [P, M], cache).  x: delayed samples [P, M].  jitter: see _jittered."""
     q = bf16 if bf else (lambda a: np.asarray(a, dtype=np.float64))
     W = {k: q(v) for k, v in params.items() if k.startswith("W")}
     b = {k: np.asarray(v, np.float64) for k, v in params.items() if k.startswith("b")}
-    a0 = q(normalise(x))[:, None, :]
-    z1 = conv(a0, W["W1"], b["b1"])
+    a0 = q(_jittered(normalise(x), jitter, x.shape[1]))[:, None, :]
+    z1 = _jittered(conv(a0, W["W1"], b["b1"]), jitter, KS)
     a1 = q(np.maximum(z1, 0.0))
-    z2 = conv(a1, W["W2"], b["b2"])
+    z2 = _jittered(conv(a1, W["W2"], b["b2"]), jitter, C * KS)
     a2 = q(np.maximum(z2, 0.0))
-    z3 = conv(a2, W["W3"], b["b3"])
+    z3 = _jittered(conv(a2, W["W3"], b["b3"]), jitter, C * KS)
     a3 = q(np.maximum(z3, 0.0))
-    w = conv(a3, W["W4"], b["b4"])[:, 0, :]
-    cache = dict(W=W, a0=a0, z1=z1, a1=a1, z2=z2, a2=a2, z3=z3, a3=a3, bf=bf)
+    w = _jittered(conv(a3, W["W4"], b["b4"])[:, 0, :], jitter, C * KS)
+    cache = dict(W=W, a0=a0, z1=z1, a1=a1, z2=z2, a2=a2, z3=z3, a3=a3, bf=bf, jitter=jitter)
     return w, cache
 
 
@@ -118,13 +128,14 @@ def backward(params, cache, w: np.ndarray, target: np.ndarray):
     P, M = w.shape
     W = cache["W"]
     g = (2.0 * M * M / (P * M)) * (w - np.asarray(target, np.float64))
-    g4 = q(g)[:, None, :]
+    jit = cache.get("jitter")
+    g4 = q(_jittered(g, jit, 1))[:, None, :]
     dW4, db4, da3 = _conv_backward(g4, cache["a3"], W["W4"])
-    g3 = q(da3 * (cache["z3"] > 0))
+    g3 = q(_jittered(da3, jit, KS) * (cache["z3"] > 0))
     dW3, db3, da2 = _conv_backward(g3, cache["a2"], W["W3"])
-    g2 = q(da2 * (cache["z2"] > 0))
+    g2 = q(_jittered(da2, jit, C * KS) * (cache["z2"] > 0))
     dW2, db2, da1 = _conv_backward(g2, cache["a1"], W["W2"])
-    g1 = q(da1 * (cache["z1"] > 0))
+    g1 = q(_jittered(da1, jit, C * KS) * (cache["z1"] > 0))
     dW1, db1, _ = _conv_backward(g1, cache["a0"], W["W1"])
     return {"W1": dW1, "b1": db1, "W2": dW2, "b2": db2, "W3": dW3, "b3": db3, "W4": dW4, "b4": db4}
 
