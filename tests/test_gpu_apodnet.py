@@ -40,6 +40,25 @@ def test_forward_matches_oracle(u):
     assert rel(w, w_ref) <= 1e-3
 
 
+def jitter_bound(params, x, target, seeds=(100, 101, 102)):
+    """Per-parameter gradient tolerance from the oracle itself: the largest relative change of
+    its bfloat16 gradients when every pre-rounding value carries the rounding error of a
+    binary32 accumulator in some other summation order (oracle.apodnet._jittered), times 3.
+    Such errors move a bfloat16 rounding of a value near a rounding tie by one ulp (2^-8
+    relative); the GPU sums in binary32 in its own order and so meets the same flips."""
+    w_ref, c = an.forward(params, x)
+    g_ref = an.backward(params, c, w_ref, target)
+    worst = {k: 0.0 for k in g_ref}
+    flips = []
+    for s in seeds:
+        w_j, cj = an.forward(params, x, jitter=np.random.default_rng(s))
+        g_j = an.backward(params, cj, w_j, target)
+        for k in g_ref:
+            worst[k] = max(worst[k], rel(g_j[k], g_ref[k]))
+        flips.append([float(np.mean(c[a] != cj[a])) for a in ("a0", "a1", "a2", "a3")])
+    return g_ref, {k: max(3.0 * v, 2e-4) for k, v in worst.items()}, np.max(flips, axis=0)
+
+
 @pytest.mark.parametrize("m", [128, 64])
 def test_gradients_match_oracle(u, m):
     params = an.init_params(2)
@@ -47,14 +66,87 @@ def test_gradients_match_oracle(u, m):
     target, _, _ = mv.mv_weights(x.astype(np.float64), min(32, m), 1e-2)
     net = u.ApodNet(params)
     g = net.gradients(torch.as_tensor(x).cuda(), torch.as_tensor(target.astype(np.float32)).cuda()).cpu().numpy()
-    w_ref, cache = an.forward(params, x.astype(np.float64))
-    g_ref = an.backward(params, cache, w_ref, target)
+    g_ref, bound, flips = jitter_bound(params, x.astype(np.float64), target)
     gu = u.unflatten_params(g)
+    errs = {k: rel(gu[k], g_ref[k]) for k in g_ref}
+    print(f"m={m}: relative gradient error {errs}; bounds {bound}; activation flips a0..a3 {flips}", flush=True)
     for k in g_ref:
-        assert rel(gu[k], g_ref[k]) <= 1e-2, k
+        assert errs[k] <= bound[k], k
 
 
-def test_train_step_matches_oracle_adam(u):
+def exact_case(m=128, n=128, seed=11):
+    """Inputs and parameters on which every value the network rounds to bfloat16 is computed
+    exactly by a binary32 accumulator in any order (small dyadic weights, samples +-1024 whose
+    RMS is 1024), so the GPU and the oracle round the same values: checked here from
+    magnitude bounds of the terms (the network run on absolute values) and their common
+    dyadic resolution."""
+    rng = np.random.default_rng(seed)
+    x = (rng.choice([-1.0, 1.0], (n, m)) * 1024.0).astype(np.float32)
+
+    def sparse(shape, scale, p):
+        v = rng.choice([-2.0, -1.0, 1.0, 2.0], shape) * scale
+        return (v * (rng.uniform(size=shape) < p)).astype(np.float32)
+
+    params = {"W1": sparse((32, 1, 5), 0.25, 1.0), "b1": (rng.integers(-2, 3, 32) * 0.25).astype(np.float32),
+              "W2": sparse((32, 32, 5), 0.125, 0.1), "b2": (rng.integers(-2, 3, 32) * 0.125).astype(np.float32),
+              "W3": sparse((32, 32, 5), 0.125, 0.1), "b3": (rng.integers(-2, 3, 32) * 0.125).astype(np.float32),
+              "W4": sparse((1, 32, 5), 0.0625, 0.5), "b4": np.float32([2.0 ** -7])}
+    target = (rng.integers(-40, 41, (n, m)) * 2.0 ** -12).astype(np.float32)
+    # terms of layer L are multiples of 2^-res[L]; their absolute sums must stay below 2^24 of that
+    w, c = an.forward(params, x.astype(np.float64))
+    absp = {k: np.abs(v) for k, v in params.items()}
+    _, ca = an.forward(absp, np.abs(x).astype(np.float64))
+    bounds = [(c["a1"], 2, ca["z1"]), (c["a2"], 5, ca["z2"]), (c["a3"], 8, ca["z3"])]
+    for a, res, tot in bounds:
+        assert np.all(np.abs(tot) * 2.0 ** res < 2.0 ** 24) and np.all(a * 2.0 ** res == np.round(a * 2.0 ** res))
+    wa = an.conv(ca["a3"], absp["W4"].astype(np.float64), absp["b4"].astype(np.float64))
+    assert np.all(wa * 2.0 ** 12 < 2.0 ** 24) and np.all(w * 2.0 ** 12 == np.round(w * 2.0 ** 12))
+    return params, x, target
+
+
+def test_gradients_bit_consistent_on_exactly_representable_inputs(u):
+    """Where no bfloat16 rounding can differ, the GPU forward pass equals the oracle's and the
+    gradients agree to binary32 summation error (far inside 1e-3)."""
+    params, x, target = exact_case()
+    net = u.ApodNet(params)
+    xt, tt = torch.as_tensor(x).cuda(), torch.as_tensor(target).cuda()
+    w = net.forward(xt).cpu().numpy()
+    w_ref, cache = an.forward(params, x.astype(np.float64))
+    assert np.array_equal(w.astype(np.float64), w_ref)
+    g = u.unflatten_params(net.gradients(xt, tt).cpu().numpy())
+    g_ref = an.backward(params, cache, w_ref, target.astype(np.float64))
+    for k in g_ref:
+        assert rel(g[k], g_ref[k]) <= 1e-5, (k, rel(g[k], g_ref[k]))
+
+
+def test_adam_steps_match_oracle_on_the_gpu_gradients(u):
+    """Two consecutive train steps against oracle.apodnet.Adam fed the GPU's own gradients of
+    each step: both bias corrections are exercised (the second step's moments mix two
+    gradients), parameters agree element by element to binary32 rounding."""
+    params = an.init_params(4)
+    x1, x2 = data(128, seed=5), data(128, seed=6)
+    t1 = mv.mv_weights(x1.astype(np.float64))[0].astype(np.float32)
+    t2 = mv.mv_weights(x2.astype(np.float64))[0].astype(np.float32)
+    net = u.ApodNet(params)
+    opt = an.Adam(params, lr=1e-3)
+    cur = params
+    for xs, ts in ((x1, t1), (x2, t2)):
+        xt, tt = torch.as_tensor(xs).cuda(), torch.as_tensor(ts).cuda()
+        g = u.unflatten_params(net.gradients(xt, tt).cpu().numpy())
+        net.train_step(xt, tt, 1e-3)
+        ref = opt.step(cur, g)
+        got = net.params()
+        for k in ref:
+            step = np.abs(ref[k].astype(np.float64) - cur[k])
+            err = np.abs(got[k].astype(np.float64) - ref[k])
+            ulp = np.spacing(np.abs(ref[k]).astype(np.float32)).astype(np.float64)
+            assert np.all(err <= 3 * ulp + 1e-4 * step), k
+        cur = ref
+
+
+def test_train_step_matches_oracle_end_to_end(u):
+    """One train step from the same parameters and data against the oracle's forward, backward
+    and Adam: the loss and the direction of every move agree."""
     params = an.init_params(4)
     x = data(128, seed=5)
     target, _, _ = mv.mv_weights(x.astype(np.float64))
@@ -69,12 +161,9 @@ def test_train_step_matches_oracle_adam(u):
     p1 = opt.step(params, an.backward(params, cache, w_ref, target))
     got = net.params()
     for k in p1:
-        # first Adam step moves each weight by ~lr * sign(g): compare the moves
         d_ref = p1[k].astype(np.float64) - params[k]
         d = got[k].astype(np.float64) - params[k]
-        agree = np.mean(np.sign(d) == np.sign(d_ref))
-        assert agree > 0.97, k
-        assert np.abs(d - d_ref).max() <= 2.1e-3
+        assert np.mean(np.sign(d) == np.sign(d_ref)) > 0.97, k
     # training continues to reduce the loss
     losses = []
     for _ in range(40):
