@@ -340,6 +340,44 @@ int usbf_mv_weights_averaged(const float* x, int32_t n_pix, int32_t n_avg, int32
                              float loading, float* w_full, float* y, hipStream_t stream);
 
 /*
+ * Analytic signal of channel traces, the input of the complex (analytic-signal) minimum-
+ * variance estimator below (not in the paper; the usual form of that estimator): for each of
+ * n_rows int16 traces of length n,
+ *   za = IDFT( H . DFT(rf) ),  H as in usbf_envelope (circular over the trace, no padding),
+ * written as binary32 (re, im) pairs.
+ *   rf  int16 [n_rows][n] (e.g. [n_frames][n_tx][n_el][n_samples] with n_rows = n_frames n_tx n_el)
+ *   za  float [n_rows][n][2]
+ * 8 <= n <= 4096 and every prime factor of n at most 31.
+ */
+int usbf_analytic_channels(const int16_t* rf, int64_t n_rows, int32_t n, float* za, hipStream_t stream);
+
+/*
+ * Delayed complex samples: usbf_delay_gather applied to analytic channel data, the same
+ * taps (binary32 delay rule; linear interpolation of the real and imaginary parts at the same
+ * fraction; 0 outside the record, for out-of-range pixels and for lines without a transmit).
+ *   za  float [n_frames][n_tx][n_el][n_samples][2] (usbf_analytic_channels output)
+ *   pix int32 [n_pix][3] (frame, line, depth index)
+ *   z   float [n_pix][n_el][2]
+ */
+int usbf_delay_gather_complex(const float* za, int32_t n_frames, const usbf_geometry* geom, const usbf_rx* rx,
+                              const int32_t* pix, int32_t n_pix, float* z, hipStream_t stream);
+
+/*
+ * Minimum variance on the delayed analytic signal (the complex form of usbf_mv_weights, not
+ * in the paper): the Hermitian spatially smoothed covariance
+ *   R = (1/K) sum_l z_l z_l^H,  z_l = z[l .. l+subap-1], K = n_el - subap + 1       (binary32)
+ *   (R + loading * trace(R)/subap * I) v = 1 by the complex Cholesky factorisation R = C C^H
+ *                                                                                    (binary64)
+ *   w = v / 1^T v;  w_full[e] = (1/K) sum_{l: 0 <= e-l < subap} w[e-l];  y = w_full^H z
+ * (all-zero pixels: uniform weights, as usbf_mv_weights).  |y| is the pixel's envelope.  For
+ * real z the results are those of usbf_mv_weights (imaginary parts 0).
+ *   z      float [n_pix][n_el][2];  w_full float [n_pix][n_el][2] or NULL;  y float [n_pix][2] or NULL.
+ * subap must be 32 and subap <= n_el <= 256.
+ */
+int usbf_mv_weights_complex(const float* z, int32_t n_pix, int32_t n_el, int32_t subap, float loading,
+                            float* w_full, float* y, hipStream_t stream);
+
+/*
  * Learned apodization: a 1D convolutional network -- four layers, 32 channels, kernel 5,
  * ReLU between layers, "same" zero padding -- maps the delayed samples x of a pixel
  * (normalised by their RMS) to one weight per element; trained to reproduce minimum-variance

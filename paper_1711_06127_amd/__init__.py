@@ -75,6 +75,9 @@ _SIGS = {
     "usbf_delay_gather_depths": (I32, [P, I32, P, P, P, I32, I32, P, P]),
     "usbf_mv_weights": (I32, [P, I32, I32, I32, F32, P, P, P]),
     "usbf_mv_weights_averaged": (I32, [P, I32, I32, I32, I32, F32, P, P, P]),
+    "usbf_analytic_channels": (I32, [P, I64, I32, P, P]),
+    "usbf_delay_gather_complex": (I32, [P, I32, P, P, P, I32, P, P]),
+    "usbf_mv_weights_complex": (I32, [P, I32, I32, I32, F32, P, P, P]),
     "usbf_apodnet_state_bytes": (ctypes.c_size_t, []),
     "usbf_apodnet_num_params": (I32, []),
     "usbf_apodnet_init": (I32, [P, P, P]),
@@ -434,6 +437,45 @@ def mv_weights_averaged(x: torch.Tensor, subap: int = 32, loading: float = 1e-2,
     wf = torch.empty((n, m), dtype=torch.float32, device=x.device) if want_weights else None
     y = torch.empty(n, dtype=torch.float32, device=x.device)
     _check(lib().usbf_mv_weights_averaged(_ptr(x), n, t, m, subap, loading, _ptr(wf), _ptr(y), _stream(x.device)))
+    return wf, y
+
+
+def analytic_channels(rf: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Analytic signal of every channel trace (last axis) of int16 rf: complex64 of rf's shape."""
+    _need_cuda(rf, "rf", torch.int16)
+    n = rf.shape[-1]
+    rows = rf.numel() // n
+    if out is None:
+        out = torch.empty(rf.shape, dtype=torch.complex64, device=rf.device)
+    _need_cuda(out, "out", torch.complex64)
+    if tuple(out.shape) != tuple(rf.shape):
+        raise ValueError(f"out must be {tuple(rf.shape)}")
+    _check(lib().usbf_analytic_channels(_ptr(rf), rows, n, _ptr(out), _stream(rf.device)))
+    return out
+
+
+def delay_gather_complex(za: torch.Tensor, dg: DeviceGeometry, pix: torch.Tensor) -> torch.Tensor:
+    """Delayed complex samples z [n_pix, n_el] (complex64) of analytic channel data za
+    complex64 [n_frames, n_tx, n_el, n_samples] at pixels pix int32 [n_pix, 3]."""
+    _need_cuda(za, "za", torch.complex64)
+    if za.dim() == 3:
+        za = za.unsqueeze(0)
+    _need_cuda(pix, "pix", torch.int32)
+    n = pix.shape[0]
+    out = torch.empty((n, dg.n_el), dtype=torch.complex64, device=za.device)
+    _check(lib().usbf_delay_gather_complex(_ptr(za), za.shape[0], ctypes.byref(dg.geom), ctypes.byref(dg.rx),
+                                           _ptr(pix), n, _ptr(out), _stream(za.device)))
+    return out
+
+
+def mv_weights_complex(z: torch.Tensor, subap: int = 32, loading: float = 1e-2, want_weights: bool = True):
+    """Minimum variance on complex delayed samples z complex64 [n_pix, n_el]:
+    (w_full complex64 [n_pix, n_el] or None, y complex64 [n_pix]), y = w_full^H z."""
+    _need_cuda(z, "z", torch.complex64)
+    n, m = z.shape
+    wf = torch.empty_like(z) if want_weights else None
+    y = torch.empty(n, dtype=torch.complex64, device=z.device)
+    _check(lib().usbf_mv_weights_complex(_ptr(z), n, m, subap, loading, _ptr(wf), _ptr(y), _stream(z.device)))
     return wf, y
 
 

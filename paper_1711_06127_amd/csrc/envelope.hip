@@ -430,6 +430,52 @@ __global__ __launch_bounds__(kEnvThreads) void envelope_kernel(const float* in, 
   }
 }
 
+// Analytic signal of int16 channel traces (the input of the complex minimum-variance
+// estimator): z = IDFT(H . DFT(x)) per row, written as (re, im) pairs.  The same transform
+// and weights as the envelope, with the final conjugation of the inverse-by-forward
+// transform applied instead of the magnitude.  Rows of up to kMaxAnalyticLength samples:
+// three n-point complex buffers in up to 104 KB of LDS.
+constexpr int kMaxAnalyticLength = 4096;
+
+template <bool PRIMES>
+__global__ __launch_bounds__(kEnvThreads) void analytic_kernel(const int16_t* __restrict__ in, int64_t n_rows,
+                                                               FftPlan P, c32* __restrict__ out) {
+  extern __shared__ c32 lds[];
+  const int n = P.n;
+  const int np = padded_len(n);
+  c32* buf[2] = {lds, lds + np};
+  c32* tw = lds + 2 * np;
+  for (int k = threadIdx.x; k < n; k += kEnvThreads) {
+    float s, c;
+    sincospif(2.0f * float(k) / float(n), &s, &c);
+    tw[pad(k)] = {c, -s};
+  }
+  const int half = n / 2;
+  const bool even = (n % 2) == 0;
+  const float inv_n = 1.0f / float(n);
+  for (int64_t row = blockIdx.x; row < n_rows; row += gridDim.x) {
+    const int16_t* x = in + row * n;
+    for (int k = threadIdx.x; k < n; k += kEnvThreads) buf[0][pad(k)] = {float(x[k]), 0.0f};
+    __syncthreads();
+    const int cur = fft_lds<PRIMES>(buf[0], buf[1], tw, P);
+    c32* X = buf[cur];
+    for (int k = threadIdx.x; k < n; k += kEnvThreads) {
+      const float hk = (k == 0 || (even && k == half)) ? 1.0f : (k < (n + 1) / 2 ? 2.0f : 0.0f);
+      const c32 v = X[pad(k)];
+      X[pad(k)] = {v.x * hk, -v.y * hk};
+    }
+    __syncthreads();
+    const int cur2 = fft_lds<PRIMES>(X, buf[cur ^ 1], tw, P);
+    const c32* Y = (cur2 == 0) ? X : buf[cur ^ 1];
+    c32* z = out + row * n;
+    for (int k = threadIdx.x; k < n; k += kEnvThreads) {
+      const c32 v = Y[pad(k)];
+      z[k] = {v.x * inv_n, -v.y * inv_n};
+    }
+    __syncthreads();  // the next row overwrites the buffers
+  }
+}
+
 int make_fft_plan(int n, FftPlan* P) {
   P->n = n;
   P->n_stages = 0;
@@ -478,6 +524,37 @@ int envelope_enqueue(const float* in, int64_t n_rows, int n, float* env, float* 
 }
 
 }  // namespace usbf
+
+extern "C" int usbf_analytic_channels(const int16_t* rf, int64_t n_rows, int32_t n, float* za, hipStream_t stream) {
+  using namespace usbf;
+  USBF_REQUIRE(rf && za, USBF_EINVAL, "null rf or za");
+  USBF_REQUIRE(n_rows >= 1, USBF_EINVAL, "n_rows must be >= 1");
+  USBF_REQUIRE(n >= 8 && n <= kMaxAnalyticLength, USBF_EUNSUPPORTED, "trace length %d outside 8..%d", n,
+               kMaxAnalyticLength);
+  FftPlan P;
+  USBF_REQUIRE(make_fft_plan(n, &P) == USBF_OK, USBF_EUNSUPPORTED, "trace length %d has a prime factor above 31", n);
+  bool primes = false;
+  for (int k = 0; k < P.n_stages; ++k) primes = primes || (P.radix[k] > 5 && P.radix[k] != 8);
+  const size_t lds = size_t(3) * padded_len(n) * sizeof(c32);
+  const void* fn = primes ? reinterpret_cast<const void*>(&analytic_kernel<true>)
+                          : reinterpret_cast<const void*>(&analytic_kernel<false>);
+  if (lds > 65536) {
+    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    USBF_REQUIRE(e == hipSuccess, USBF_EDEVICE, "hipFuncSetAttribute: %s", hipGetErrorString(e));
+  }
+  int dev = 0, n_cu = 256;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+  const int per_cu = std::max(1, std::min(8, int(163840 / (lds + 64))));
+  const int64_t blocks = std::min<int64_t>(n_rows, int64_t(n_cu) * per_cu);
+  c32* out = reinterpret_cast<c32*>(za);
+  if (primes)
+    hipLaunchKernelGGL((analytic_kernel<true>), dim3(unsigned(blocks)), dim3(kEnvThreads), lds, stream, rf, n_rows, P,
+                       out);
+  else
+    hipLaunchKernelGGL((analytic_kernel<false>), dim3(unsigned(blocks)), dim3(kEnvThreads), lds, stream, rf, n_rows,
+                       P, out);
+  return check_launch("analytic_kernel");
+}
 
 extern "C" int usbf_envelope(const float* in, int64_t n_rows, int32_t n, float* env, float* row_max,
                              hipStream_t stream) {

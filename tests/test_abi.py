@@ -126,6 +126,24 @@ def test_mv_rejects(u):
     assert L.usbf_mv_weights_averaged(FAKE, 4, 0, 128, 32, 1e-2, FAKE, FAKE, None) == -1
     assert L.usbf_mv_weights_averaged(FAKE, 4, 257, 128, 32, 1e-2, FAKE, FAKE, None) == -1
     assert L.usbf_mv_weights_averaged(FAKE, 4, 5, 128, 32, 1e-2, None, None, None) == -1
+    assert L.usbf_mv_weights_complex(None, 4, 128, 32, 1e-2, FAKE, FAKE, None) == -1
+    assert L.usbf_mv_weights_complex(FAKE, 4, 128, 16, 1e-2, FAKE, FAKE, None) == -3
+    assert L.usbf_mv_weights_complex(FAKE, 4, 16, 32, 1e-2, FAKE, FAKE, None) == -3     # fewer elements than L
+    assert L.usbf_mv_weights_complex(FAKE, 0, 128, 32, 1e-2, FAKE, FAKE, None) == -1
+
+
+def test_analytic_and_complex_gather_reject(u):
+    L = u.lib()
+    assert L.usbf_analytic_channels(None, 4, 1024, FAKE, None) == -1
+    assert L.usbf_analytic_channels(FAKE, 0, 1024, FAKE, None) == -1
+    assert L.usbf_analytic_channels(FAKE, 4, 4, FAKE, None) == -3
+    assert L.usbf_analytic_channels(FAKE, 4, 8192, FAKE, None) == -3          # longer than 4096
+    assert L.usbf_analytic_channels(FAKE, 4, 37 * 64, FAKE, None) == -3       # prime factor 37
+    g, r = geom(u), rx(u)
+    assert L.usbf_delay_gather_complex(None, 1, ctypes.byref(g), ctypes.byref(r), FAKE, 4, FAKE, None) == -1
+    assert L.usbf_delay_gather_complex(FAKE, 1, ctypes.byref(g), ctypes.byref(r), FAKE, 0, FAKE, None) == -1
+    assert L.usbf_delay_gather_complex(FAKE, 1, ctypes.byref(g), ctypes.byref(rx(u, c=-1.0)), FAKE, 4, FAKE,
+                                       None) == -1
 
 
 def test_bmode_noalloc_rejects_requests_beyond_its_scratch(u):

@@ -350,9 +350,9 @@ def test_delay_gather_out_of_range_pixels_give_zeros(usbf):
 
 
 def test_mv_weights_match_oracle(usbf):
-    """Binary32 covariance, binary64 Cholesky: weights within 1e-2 (relative 2-norm; the loaded
-    matrix has condition number <= 1 + L/loading = 3201) and outputs within 1e-3 of the
-    float64 oracle on the same binary32 inputs."""
+    """Binary32 covariance, binary64 Cholesky, binary32 expansion and sum: weights within 1e-2
+    (relative 2-norm; the loaded matrix has condition number <= 1 + L/loading = 3201) and
+    outputs within 1e-3 of the float64 oracle on the same binary32 inputs."""
     from oracle import mv
     g = synth.config_multiline_2d()
     rf = sim(g, 3200)
@@ -360,10 +360,10 @@ def test_mv_weights_match_oracle(usbf):
     rng = np.random.default_rng(1)
     m = 2000
     pix = np.stack([np.zeros(m, int), rng.integers(0, g.n_lines, m), rng.integers(200, g.n_depth, m)], 1)
-    x = usbf.delay_gather(rf, dg, torch.as_tensor(pix, dtype=torch.int32).cuda())
-    wf, y = usbf.mv_weights(x, 32, 1e-2)
-    xr = x.cpu().numpy().astype(np.float64)
-    wf_ref, y_ref, _ = mv.mv_weights(xr, 32, 1e-2)
+    # both sides solve for the same binary32 samples: the oracle's gather, rounded
+    x32 = oracle.delay_gather(g, rf.cpu().numpy(), pix).astype(np.float32)
+    wf, y = usbf.mv_weights(torch.as_tensor(x32).cuda(), 32, 1e-2)
+    wf_ref, y_ref, _ = mv.mv_weights(x32.astype(np.float64), 32, 1e-2)
     wf = wf.cpu().numpy()
     rel = np.linalg.norm(wf - wf_ref, axis=1) / np.linalg.norm(wf_ref, axis=1)
     assert np.median(rel) < 1e-3 and rel.max() < 1e-2
@@ -401,9 +401,10 @@ def test_mv_weights_averaged_match_oracle(usbf):
     nb[:, :, 2] = np.clip(nb[:, :, 2] + np.arange(-2, 3)[None, :], 0, g.n_depth - 1)
     ref_x = oracle.delay_gather(g, rf.cpu().numpy(), nb.reshape(-1, 3)).reshape(m, 5, g.n_el)
     assert rel_err(x.cpu().numpy(), ref_x) <= TOL
-    wf, y = usbf.mv_weights_averaged(x, 32, 1e-2)
-    xr = x.cpu().numpy().astype(np.float64)
-    wf_ref, y_ref, _ = mv.mv_weights_averaged(xr, 32, 1e-2)
+    # both sides solve for the same binary32 samples: the oracle's gather, rounded
+    x32 = ref_x.astype(np.float32)
+    wf, y = usbf.mv_weights_averaged(torch.as_tensor(x32).cuda(), 32, 1e-2)
+    wf_ref, y_ref, _ = mv.mv_weights_averaged(x32.astype(np.float64), 32, 1e-2)
     wf = wf.cpu().numpy()
     rel = np.linalg.norm(wf - wf_ref, axis=1) / np.linalg.norm(wf_ref, axis=1)
     assert np.median(rel) < 1e-3 and rel.max() < 1e-2
