@@ -405,6 +405,15 @@ int usbf_apodnet_train_step(void* state, const float* x, const float* w_target, 
                             float lr, float* loss, void* ws, size_t ws_bytes, hipStream_t stream);
 int usbf_apodnet_gradients(const void* state, const float* x, const float* w_target, int32_t n_pix, int32_t n_el,
                            float* grad, void* ws, size_t ws_bytes, hipStream_t stream);
+/*
+ * Learned apodization applied in one pass: the network's weights for each pixel and the
+ * weighted sum y[p] = sum_e w[p][e] x[p][e] (usbf_beamform_weighted, with y_fallback[p] where a
+ * weight is not finite), without writing the weights unless w is given.
+ *   x float [n_pix][n_el]; y_fallback float [n_pix] or NULL; w float [n_pix][n_el] or NULL;
+ *   y float [n_pix].  No workspace.
+ */
+int usbf_apodnet_apply(const void* state, const float* x, int32_t n_pix, int32_t n_el, const float* y_fallback,
+                       float* w, float* y, hipStream_t stream);
 
 /*
  * Adaptively weighted sum: y[p] = sum_e w[p][e] x[p][e]; a pixel whose weights are not all

@@ -84,6 +84,7 @@ _SIGS = {
     "usbf_apodnet_forward": (I32, [P, P, I32, I32, P, P, ctypes.c_size_t, P]),
     "usbf_apodnet_train_step": (I32, [P, P, P, I32, I32, F32, P, P, ctypes.c_size_t, P]),
     "usbf_apodnet_gradients": (I32, [P, P, P, I32, I32, P, P, ctypes.c_size_t, P]),
+    "usbf_apodnet_apply": (I32, [P, P, I32, I32, P, P, P, P]),
     "usbf_beamform_weighted": (I32, [P, P, P, I32, I32, P, P]),
     "usbf_batch_plan_create": (I32, [P, I32, ctypes.c_char_p, P, P]),
     "usbf_batch_run": (I32, [P, P]),
@@ -531,6 +532,18 @@ class ApodNet:
         ws = self._workspace(n, m, False)
         _check(lib().usbf_apodnet_forward(_ptr(self.state), _ptr(x), n, m, _ptr(out), _ptr(ws), ws.numel(),
                                           _stream(x.device)))
+        return out
+
+    def apply(self, x: torch.Tensor, fallback: torch.Tensor | None = None, out: torch.Tensor | None = None,
+              w_out: torch.Tensor | None = None) -> torch.Tensor:
+        """Network weights and the weighted sum in one pass: y [n_pix] (fallback[p] where a weight
+        is not finite); the weights go to w_out if given."""
+        _need_cuda(x, "x", torch.float32)
+        n, m = x.shape
+        if out is None:
+            out = torch.empty(n, dtype=torch.float32, device=x.device)
+        _check(lib().usbf_apodnet_apply(_ptr(self.state), _ptr(x), n, m, _ptr(fallback), _ptr(w_out), _ptr(out),
+                                        _stream(x.device)))
         return out
 
     def train_step(self, x: torch.Tensor, target: torch.Tensor, lr: float = 1e-3,

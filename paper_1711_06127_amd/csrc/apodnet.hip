@@ -94,6 +94,13 @@ __global__ void pack_kernel(NetState st) {
     (void)steps;
     const int rel = idx - base;
     const int s = rel / kStepElems, lane = (rel % kStepElems) / 8, e = rel % 8;
+    if (base == kPkF4) {
+      // forward output layer as a product over channels only: A[t][ci] = W4[0][ci][t] (two
+      // k-steps of 16 channels; rows t >= 5 and the remaining steps are zero)
+      const int t = lane % 32, ci = 16 * s + 8 * (lane / 32) + e;
+      st.packed[idx] = __bf16((s < 2 && t < kKS) ? p[kW4 + ci * kKS + t] : 0.0f);
+      continue;
+    }
     const int off = layer == 1 ? kW1 : layer == 2 ? kW2 : layer == 3 ? kW3 : kW4;
     const int lci = (layer == 1) ? 1 : 32;  // the layer's own input channels
     // forward: W[co][ci][t]; data gradient: W'[ci'][co'][t'] = W[co'][ci'][4 - t'] with the
@@ -180,114 +187,213 @@ __global__ __launch_bounds__(kNetThreads) void conv_kernel(const __bf16* __restr
 
 // ---------------------------------------------------------------- fused forward
 
-// The whole forward pass of one pixel in one wave, activations kept in LDS: normalise into a0,
-// then the four convolutions, each layer's 32-position tiles read from one LDS buffer and
-// written (bias, ReLU, bf16) into the other.  The packed weights of all four layers stay in
-// registers for the wave's lifetime.  With SAVE the layer inputs a0..a3 are also written to
-// global memory for the backward pass.
-// LDS per wave: a0 [M + 16] bf16 (position m at index m + 2, zeros around), two buffers
-// [M + 4][32] bf16 (position m at row m + 2; rows 0, 1, M + 2, M + 3 stay zero).
+// The whole forward pass of one pixel in one workgroup of four waves, activations kept in LDS:
+// normalise into a0, then the four convolutions; wave v computes the 32-position tiles
+// v, v + 4, ... of every layer.  Each product is issued transposed, D[co][position] =
+// W[co][kappa] act[kappa][position] (the packed weights serve as the A operand: the MFMA lane
+// layouts of A and B coincide), so that every lane ends with four runs of four consecutive
+// channels of one position, stored with 8-byte LDS writes.  The one-channel output layer is
+// computed as Z[t][position] = sum_ci W4[ci][t] a3[position][ci] (two k-steps instead of ten)
+// and w[m] = b4 + sum_t Z[t][m + t - 2] on the vector ALUs.  The packed weights stay in
+// registers for the workgroup's lifetime, and the next pixel's samples are prefetched into
+// registers.  With SAVE the layer inputs a0..a3 are also written to global memory for the
+// backward pass; with y the weighted sum y = sum_m w[m] x[m] (the delay-and-sum fallback where
+// a weight is not finite) is formed in the same pass.
+// LDS: a0 [M + 16] bf16 (position m at index m + 2, zeros around); two buffers of M + 4 rows
+// of kRowStride bf16 (position m at row m + 2; rows 0, 1, M + 2, M + 3 stay zero; 32 channels
+// and 8 bf16 of padding, so that the 16-byte operand reads of consecutive positions spread
+// over the banks); the output layer's Z [M][8] float in the second buffer; biases; the
+// cross-wave sums.
+constexpr int kFwdThreads = 256;
+constexpr int kRowStride = kNC + 8;
+
+__host__ __device__ constexpr size_t fused_buf_elems(int M) { return size_t(M + 4) * kRowStride; }
 __host__ __device__ constexpr size_t fused_lds_bytes(int M) {
-  return (size_t(M + 16) + 2 * size_t(M + 4) * kNC) * sizeof(__bf16);
+  return (size_t(M + 16) + 2 * fused_buf_elems(M)) * sizeof(__bf16) + 3 * kNC * sizeof(float) + 64;
+}
+
+__device__ inline uint32_t pack_bf16x2(float lo, float hi) {
+  const __bf16 a = __bf16(lo), b = __bf16(hi);
+  return uint32_t(__builtin_bit_cast(uint16_t, a)) | (uint32_t(__builtin_bit_cast(uint16_t, b)) << 16);
 }
 
 template <bool SAVE>
-__global__ __launch_bounds__(64) void fused_forward_kernel(const float* __restrict__ x, int n_pix, int M,
-                                                           const __bf16* __restrict__ packed,
-                                                           const float* __restrict__ params, float* __restrict__ w,
-                                                           __bf16* __restrict__ a0g, __bf16* __restrict__ a1g,
-                                                           __bf16* __restrict__ a2g, __bf16* __restrict__ a3g) {
+__global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(3))) void fused_forward_kernel(
+    const float* __restrict__ x, int n_pix, int M, const __bf16* __restrict__ packed,
+    const float* __restrict__ params, float* __restrict__ w, const float* __restrict__ fallback,
+    float* __restrict__ y, __bf16* __restrict__ a0g, __bf16* __restrict__ a1g, __bf16* __restrict__ a2g,
+    __bf16* __restrict__ a3g) {
   extern __shared__ __align__(16) __bf16 lds[];
   __bf16* a0 = lds;
   __bf16* bufA = lds + (M + 16);
-  __bf16* bufB = bufA + (M + 4) * kNC;
-  const int lane = threadIdx.x;
-  const int j = lane % 32, hi = lane / 32, i = lane % 32;
+  __bf16* bufB = bufA + fused_buf_elems(M);
+  float* zb = reinterpret_cast<float*>(bufB + 2 * kRowStride);              // [M][8], bufB past its zero rows
+  float* bias = reinterpret_cast<float*>(bufB + fused_buf_elems(M));        // [3][32]
+  float* red = bias + 3 * kNC;                                              // [4] sums + [4] flags
+  const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+  const int j = lane % 32, hi = lane / 32;
   const int n_mt = M / 32;
 
   const bf16x8 w1 = *reinterpret_cast<const bf16x8*>(packed + kPkF1 + lane * 8);
-  bf16x8 w2[10], w3[10], w4[10];
+  bf16x8 w2[10], w3[10], w4[2];
 #pragma unroll
   for (int s = 0; s < 10; ++s) {
     w2[s] = *reinterpret_cast<const bf16x8*>(packed + kPkF2 + (s * 64 + lane) * 8);
     w3[s] = *reinterpret_cast<const bf16x8*>(packed + kPkF3 + (s * 64 + lane) * 8);
-    w4[s] = *reinterpret_cast<const bf16x8*>(packed + kPkF4 + (s * 64 + lane) * 8);
   }
-  const float b1 = params[kB1 + j], b2 = params[kB2 + j], b3 = params[kB3 + j], b4 = params[kB4];
-
+#pragma unroll
+  for (int s = 0; s < 2; ++s) w4[s] = *reinterpret_cast<const bf16x8*>(packed + kPkF4 + (s * 64 + lane) * 8);
+  const float b4 = params[kB4];
+  if (tid < 3 * kNC) bias[tid] = params[(tid < kNC ? kB1 : tid < 2 * kNC ? kB2 - kNC : kB3 - 2 * kNC) + tid];
   // zero margins (never written afterwards)
-  for (int k = lane; k < 16; k += 64) a0[k < 2 ? k : M + k] = __bf16(0.0f);  // 0, 1, M + 2 .. M + 15
-  for (int k = lane; k < 4 * kNC; k += 64) {
-    const int row = k / kNC < 2 ? k / kNC : M + k / kNC;  // rows 0, 1, M + 2, M + 3
-    bufA[row * kNC + k % kNC] = __bf16(0.0f);
-    bufB[row * kNC + k % kNC] = __bf16(0.0f);
+  if (tid < 16) a0[tid < 2 ? tid : M + tid] = __bf16(0.0f);  // 0, 1, M + 2 .. M + 15
+  for (int k = tid; k < 4 * kRowStride; k += kFwdThreads) {
+    const int row = k / kRowStride < 2 ? k / kRowStride : M + k / kRowStride;  // rows 0, 1, M + 2, M + 3
+    bufA[row * kRowStride + k % kRowStride] = __bf16(0.0f);
+    bufB[row * kRowStride + k % kRowStride] = __bf16(0.0f);
   }
 
-  // 32 x 32 channel layer from `src` into `dst` (bias + ReLU) or, for the last layer, into w
-  auto layer32 = [&](const __bf16* src, const bf16x8* wk, auto last_, float bias, __bf16* dst, float* wout) {
-    constexpr bool LAST = decltype(last_)::value;
-    for (int mt = 0; mt < n_mt; ++mt) {
-      f32x16 acc = {};
+  // accumulator initialised with the biases of the 16 channels this lane's rows hold
+  auto bias_init = [&](int layer) {
+    f32x16 acc;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float4 b = *reinterpret_cast<const float4*>(bias + layer * kNC + 8 * q + 4 * hi);
+      acc[4 * q + 0] = b.x;
+      acc[4 * q + 1] = b.y;
+      acc[4 * q + 2] = b.z;
+      acc[4 * q + 3] = b.w;
+    }
+    return acc;
+  };
+  // ReLU, bf16 and the four 8-byte stores of a tile's D[co][position] into dst
+  auto store_relu = [&](const f32x16& acc, int mt, __bf16* dst) {
+    __bf16* row = dst + (32 * mt + j + 2) * kRowStride + 4 * hi;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      uint2 v;
+      v.x = pack_bf16x2(fmaxf(acc[4 * q + 0], 0.0f), fmaxf(acc[4 * q + 1], 0.0f));
+      v.y = pack_bf16x2(fmaxf(acc[4 * q + 2], 0.0f), fmaxf(acc[4 * q + 3], 0.0f));
+      *reinterpret_cast<uint2*>(row + 8 * q) = v;
+    }
+  };
+  // 32 x 32 channel layer from src into dst
+  auto layer32 = [&](const __bf16* src, const bf16x8* wk, int layer, __bf16* dst) {
+    for (int mt = wave; mt < n_mt; mt += kFwdThreads / 64) {
+      f32x16 acc = bias_init(layer);
 #pragma unroll
       for (int s = 0; s < 10; ++s) {
         const int t = s / 2, ci0 = (s % 2) * 16 + 8 * hi;
-        const bf16x8 a = *reinterpret_cast<const bf16x8*>(src + (32 * mt + i + t) * kNC + ci0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, wk[s], acc, 0, 0, 0);
+        const bf16x8 b = *reinterpret_cast<const bf16x8*>(src + (32 * mt + j + t) * kRowStride + ci0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wk[s], b, acc, 0, 0, 0);
       }
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int m = 32 * mt + 8 * (r / 4) + 4 * hi + (r % 4);
-        if constexpr (LAST) {
-          if (j == 0) wout[m] = acc[r] + bias;
-        } else {
-          dst[(m + 2) * kNC + j] = __bf16(fmaxf(acc[r] + bias, 0.0f));
-        }
-      }
+      store_relu(acc, mt, dst);
     }
   };
   // copy the M rows of a 32-channel LDS buffer to global [M][32] with 16-byte stores
   auto save32 = [&](const __bf16* buf, __bf16* g) {
-    for (int k = lane; k < M * 4; k += 64)
-      reinterpret_cast<uint4*>(g)[k] = reinterpret_cast<const uint4*>(buf + 2 * kNC)[k];
+    for (int k = tid; k < M * 4; k += kFwdThreads)
+      reinterpret_cast<uint4*>(g)[k] = *reinterpret_cast<const uint4*>(buf + (k / 4 + 2) * kRowStride + 8 * (k % 4));
   };
 
+  // the pixel's samples, prefetched one pixel ahead: lane holds positions lane + 64 k (every
+  // wave the whole pixel, so that each forms the sum of squares itself without a cross-wave step)
+  float xr[4];
+  auto load_x = [&](int pp) {
+    const float* xp = x + size_t(pp) * M;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) xr[k] = (lane + 64 * k < M) ? xp[lane + 64 * k] : 0.0f;
+  };
+  // y of pixel q from the waves' partial sums in red
+  auto finish_y = [&](int q) {
+    float acc = 0.0f;
+    int bad = 0;
+    for (int v = 0; v < (M + 63) / 64; ++v) {
+      acc += red[v];
+      bad |= reinterpret_cast<const int*>(red)[4 + v];
+    }
+    y[q] = (bad && fallback) ? fallback[q] : acc;
+  };
+  if (int(blockIdx.x) < n_pix) load_x(blockIdx.x);
   for (int p = blockIdx.x; p < n_pix; p += gridDim.x) {
-    __syncthreads();  // the previous pixel is done with a0 and the buffers
-    const float* xp = x + size_t(p) * M;
-    float ss = 0.0f;
-    for (int m = lane; m < M; m += 64) ss = __builtin_fmaf(xp[m], xp[m], ss);
+    __syncthreads();  // the previous pixel is done with a0, the buffers and the sums
+    if (y && tid == 0 && p != int(blockIdx.x)) finish_y(p - gridDim.x);
+    float ss = 0.0f, xm = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      ss = __builtin_fmaf(xr[k], xr[k], ss);
+      xm = (k == wave) ? xr[k] : xm;  // position tid = lane + 64 wave
+    }
     for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
     const float inv = 1.0f / sqrtf(ss / float(M) + 1e-12f);
-    for (int m = lane; m < M; m += 64) {
-      const __bf16 v = __bf16(xp[m] * inv);
-      a0[m + 2] = v;
-      if constexpr (SAVE) a0g[size_t(p) * M + m] = v;
+    if (p + int(gridDim.x) < n_pix) load_x(p + gridDim.x);
+    if (tid < M) {
+      const __bf16 v = __bf16(xm * inv);
+      a0[tid + 2] = v;
+      if constexpr (SAVE) a0g[size_t(p) * M + tid] = v;
     }
     __syncthreads();
-    // layer 1 (one input channel): A[i][k] = a0[32 mt + i + k - 2] for k < 5
-    for (int mt = 0; mt < n_mt; ++mt) {
-      bf16x8 a;
+    // layer 1 (one input channel): B[k][position] = a0[position + k - 2] for k < 5
+    for (int mt = wave; mt < n_mt; mt += kFwdThreads / 64) {
+      bf16x8 b;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int k = 8 * hi + e;
-        a[e] = (k < kKS) ? a0[32 * mt + i + k] : __bf16(0.0f);
-      }
-      f32x16 acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, w1, f32x16{}, 0, 0, 0);
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int m = 32 * mt + 8 * (r / 4) + 4 * hi + (r % 4);
-        bufA[(m + 2) * kNC + j] = __bf16(fmaxf(acc[r] + b1, 0.0f));
-      }
+      for (int e = 0; e < 8; ++e) b[e] = (hi == 0 && e < kKS) ? a0[32 * mt + j + e] : __bf16(0.0f);
+      const f32x16 acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1, b, bias_init(0), 0, 0, 0);
+      store_relu(acc, mt, bufA);
     }
     __syncthreads();
     if constexpr (SAVE) save32(bufA, a1g + size_t(p) * M * kNC);
-    layer32(bufA, w2, std::false_type{}, b2, bufB, nullptr);
+    layer32(bufA, w2, 1, bufB);
     __syncthreads();
     if constexpr (SAVE) save32(bufB, a2g + size_t(p) * M * kNC);
-    layer32(bufB, w3, std::false_type{}, b3, bufA, nullptr);
+    layer32(bufB, w3, 2, bufA);
     __syncthreads();
     if constexpr (SAVE) save32(bufA, a3g + size_t(p) * M * kNC);
-    layer32(bufA, w4, std::true_type{}, b4, nullptr, w + size_t(p) * M);
+    // output layer: Z[t][position] for t < 5 (rows t of D; lane hi = 0 holds t = 0..3, hi = 1 t = 4)
+    for (int mt = wave; mt < n_mt; mt += kFwdThreads / 64) {
+      f32x16 acc = {};
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const bf16x8 b = *reinterpret_cast<const bf16x8*>(bufA + (32 * mt + j + 2) * kRowStride + 16 * s + 8 * hi);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w4[s], b, acc, 0, 0, 0);
+      }
+      float* zr = zb + (32 * mt + j) * 8;
+      if (hi == 0)
+        *reinterpret_cast<float4*>(zr) = float4{acc[0], acc[1], acc[2], acc[3]};
+      else
+        zr[4] = acc[0];
+    }
+    __syncthreads();
+    float wm = 0.0f;
+    if (tid < M) {
+      // w[m] = b4 + sum_t Z[t][m + t - 2] (positions outside the pixel contribute 0)
+      float s = 0.0f;
+#pragma unroll
+      for (int t = 0; t < kKS; ++t) {
+        const int q = tid + t - 2;
+        if (q >= 0 && q < M) s += zb[q * 8 + t];
+      }
+      wm = s + b4;
+      if (w) w[size_t(p) * M + tid] = wm;
+    }
+    if (y) {
+      // per-wave partial sums; thread 0 combines them after the next barrier (at the top of the
+      // next pixel, or after the loop), so the weighted sum costs no barrier of its own
+      float acc = tid < M ? wm * xm : 0.0f;
+      int bad = tid < M && !(fabsf(wm) < INFINITY);
+      for (int off = 32; off > 0; off >>= 1) {
+        acc += __shfl_xor(acc, off, 64);
+        bad |= __shfl_xor(bad, off, 64);
+      }
+      if (lane == 0) {
+        red[wave] = acc;
+        reinterpret_cast<int*>(red)[4 + wave] = bad;
+      }
+    }
+  }
+  if (y && int(blockIdx.x) < n_pix) {
+    __syncthreads();
+    if (tid == 0) finish_y(n_pix - 1 - (n_pix - 1 - int(blockIdx.x)) % int(gridDim.x));
   }
 }
 
@@ -543,22 +649,31 @@ static void launch_wgrad(const __bf16* g, const __bf16* a, int n_pix, int M, flo
   hipLaunchKernelGGL(reduce_grad_kernel, dim3(8), dim3(256), 0, s, part, blocks, CO, NK, w_off, b_off, grad);
 }
 
-static int fused_grid(int n_pix) {
-  int dev = 0, n_cu = 256;
+// a resident grid: as many workgroups as the compute units hold at once (the pixel loop is
+// grid-strided, so a second round of workgroups would only start when the first has finished
+// all its pixels)
+template <bool SAVE>
+static int fused_grid(int n_pix, size_t lds) {
+  int dev = 0, n_cu = 256, per_cu = 0;
   if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
-  return std::max(1, std::min(n_pix, 16 * n_cu));
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fused_forward_kernel<SAVE>, kFwdThreads, lds) !=
+          hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  return std::max(1, std::min(n_pix, per_cu * n_cu));
 }
 
-// forward pass; with `save` the layer inputs go to the workspace for the backward pass
+// forward pass; with `save` the layer inputs go to the workspace for the backward pass; with
+// y the weighted sum is formed as well (w may then be null)
 static void net_forward(const NetState& st, const float* x, int n_pix, int M, const NetWs& w, bool save,
-                        hipStream_t s) {
+                        hipStream_t s, const float* fallback = nullptr, float* y = nullptr) {
   const size_t lds = fused_lds_bytes(M);
   if (save)
-    hipLaunchKernelGGL(fused_forward_kernel<true>, dim3(fused_grid(n_pix)), dim3(64), lds, s, x, n_pix, M, st.packed,
-                       st.params, w.w, w.a0, w.a1, w.a2, w.a3);
+    hipLaunchKernelGGL(fused_forward_kernel<true>, dim3(fused_grid<true>(n_pix, lds)), dim3(kFwdThreads), lds, s, x, n_pix, M,
+                       st.packed, st.params, w.w, fallback, y, w.a0, w.a1, w.a2, w.a3);
   else
-    hipLaunchKernelGGL(fused_forward_kernel<false>, dim3(fused_grid(n_pix)), dim3(64), lds, s, x, n_pix, M, st.packed,
-                       st.params, w.w, nullptr, nullptr, nullptr, nullptr);
+    hipLaunchKernelGGL(fused_forward_kernel<false>, dim3(fused_grid<false>(n_pix, lds)), dim3(kFwdThreads), lds, s, x, n_pix, M,
+                       st.packed, st.params, w.w, fallback, y, nullptr, nullptr, nullptr, nullptr);
 }
 
 static int check_net_args(int n_pix, int M) {
@@ -599,6 +714,18 @@ extern "C" int usbf_apodnet_forward(const void* state, const float* x, int32_t n
   wsp.w = w;  // the last layer writes the caller's buffer
   net_forward(st, x, n_pix, n_el, wsp, false, stream);
   return check_launch("apodnet forward");
+}
+
+extern "C" int usbf_apodnet_apply(const void* state, const float* x, int32_t n_pix, int32_t n_el,
+                                  const float* y_fallback, float* w, float* y, hipStream_t stream) {
+  USBF_REQUIRE(state && x && y, USBF_EINVAL, "null state, x or y");
+  int st_ = check_net_args(n_pix, n_el);
+  if (st_) return st_;
+  const NetState st = carve_state(const_cast<void*>(state));
+  NetWs wsp{};
+  wsp.w = w;  // optional copy of the weights
+  net_forward(st, x, n_pix, n_el, wsp, false, stream, y_fallback, y);
+  return check_launch("apodnet apply");
 }
 
 extern "C" int usbf_apodnet_train_step(void* state, const float* x, const float* w_target, int32_t n_pix, int32_t n_el,

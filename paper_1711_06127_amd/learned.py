@@ -113,7 +113,7 @@ def beamform_lines(rf: torch.Tensor, dg: DeviceGeometry, method: str, model: Lea
         if method == "mv":
             _, y = mv_weights(x, SUBAPERTURE, LOADING, want_weights=False)
         elif method == "learned":
-            y = beamform_weighted(x, model.weights(x), fb[c0:c0 + chunk].contiguous())
+            y = model.net.apply(x, fb[c0:c0 + chunk].contiguous())
         else:
             raise ValueError(method)
         out[c0:c0 + pix.shape[0]] = y
@@ -239,59 +239,114 @@ def evaluate(model: LearnedApodization, g, dg: DeviceGeometry, n_frames: int = 3
     res["learned_vs_mv"] = {"cnr_rel": dc, "width_rel": dw,
                             "pass": bool(abs(dc) <= 0.1 and abs(dw) <= 0.1 and
                                          res["learned"]["psf_width_mm_mean"] < res["das"]["psf_width_mm_mean"])}
-    # weight-path timing on one full frame (gather excluded: both need it)
     rf, _, _ = eval_phantom(g, seed, dg.device)
-    pix = frame_pixels(dg.n_lines, dg.n_depth, 0, rf.device)[:262144]
-    x = delay_gather(rf, dg, pix)
-    for name, fn in (("mv", lambda: mv_weights(x, SUBAPERTURE, LOADING)),
-                     ("learned", lambda: model.weights(x))):
+    res["timing"] = time_paths(model, rf, dg)
+    res["eval"] = f"{n_frames} held-out frames (seeds {seed}..), 1 cyst and 8 points each"
+    return res
+
+
+def time_paths(model: LearnedApodization, rf: torch.Tensor, dg: DeviceGeometry, reps: int = 5) -> dict:
+    """GPU time of the two adaptive paths from channel data to beamformed values for every
+    pixel of one frame: delay-gather + minimum-variance weights and weighted sum (the MV
+    kernel forms y = w_full^T x itself), against delay-gather + network forward + weighted sum
+    in one pass (with the delay-and-sum value of the frame as the fallback, computed
+    beforehand; the separate forward and weighted-sum calls are timed as well).  The
+    stages both share afterwards (envelope, compression, scan conversion) are left out.  HIP
+    events on the stream the kernels run on."""
+    pix = frame_pixels(dg.n_lines, dg.n_depth, 0, rf.device)
+    n = pix.shape[0]
+    fb = beamform(rf.unsqueeze(0) if rf.dim() == 3 else rf, dg)[0].reshape(-1).contiguous()
+    x = torch.empty((n, dg.n_el), dtype=torch.float32, device=rf.device)
+    w = torch.empty_like(x)
+    y = torch.empty(n, dtype=torch.float32, device=rf.device)
+
+    def mv_path():
+        delay_gather(rf, dg, pix, out=x)
+        return mv_weights(x, SUBAPERTURE, LOADING, want_weights=False)[1]
+
+    def learned_path():
+        delay_gather(rf, dg, pix, out=x)
+        return model.net.apply(x, fb, out=y)
+
+    def learned_unfused():
+        delay_gather(rf, dg, pix, out=x)
+        model.net.forward(x, out=w)
+        return beamform_weighted(x, w, fb)
+
+    def gather_only():
+        delay_gather(rf, dg, pix, out=x)
+
+    out = {"pixels": int(n)}
+    stream = torch.cuda.current_stream(rf.device)
+    for name, fn in (("mv", mv_path), ("learned", learned_path), ("learned_unfused", learned_unfused),
+                     ("gather", gather_only)):
         fn()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(5):
+        e0.record(stream)
+        for _ in range(reps):
             fn()
-        e1.record()
+        e1.record(stream)
         torch.cuda.synchronize()
-        res[name]["weights_ms_per_262144_px"] = e0.elapsed_time(e1) / 5
-    res["eval"] = f"{n_frames} held-out frames (seeds {seed}..), 1 cyst and 8 points each"
-    return res
+        out[f"{name}_ms_per_frame"] = e0.elapsed_time(e1) / reps
+    out["learned_speedup_vs_mv"] = out["mv_ms_per_frame"] / out["learned_ms_per_frame"]
+    return out
+
+
+def simulate_training_frames(g, n: int, seed0: int = 100, device="cuda", log=None) -> torch.Tensor:
+    """n training frames, each with two random anechoic cysts (radius 2-5 mm) in speckle and
+    the workload's 20 point targets."""
+    rng = np.random.default_rng(1)
+    lx = g.line_origin[:, 0].astype(np.float64)
+    zmax = g.depth_of(g.n_depth - 1)
+    frames = []
+    for f in range(n):
+        cysts = [(rng.uniform(0.8 * lx[0], 0.8 * lx[-1]), rng.uniform(0.15, 0.85) * zmax, rng.uniform(2e-3, 5e-3))
+                 for _ in range(2)]
+        frames.append(_sim(g, seed0 + f, cysts=cysts, device=device)[0])
+        if log and (f + 1) % 16 == 0:
+            log(f"simulated {f + 1} / {n} training frames")
+    return torch.stack(frames).contiguous()
 
 
 def main():
     import synth
     ap = argparse.ArgumentParser()
-    ap.add_argument("--frames", type=int, default=16)
-    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--frames", type=str, default="16",
+                    help="training-set sizes, comma separated (each trains its own network from the same start)")
+    ap.add_argument("--steps", type=int, default=8000)
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--eval-frames", type=int, default=32)
     ap.add_argument("--save", default="")
+    ap.add_argument("--out", default="", help="also write the result JSON to this file")
     args = ap.parse_args()
     g = synth.config_multiline_2d()
     dg = DeviceGeometry(g)
-    rng = np.random.default_rng(1)
-    lx = g.line_origin[:, 0].astype(np.float64)
-    zmax = g.depth_of(g.n_depth - 1)
-    frames = []
+    sizes = [int(v) for v in args.frames.split(",")]
     t = time.perf_counter()
-    for f in range(args.frames):
-        cysts = [(rng.uniform(0.8 * lx[0], 0.8 * lx[-1]), rng.uniform(0.15, 0.85) * zmax, rng.uniform(2e-3, 5e-3))
-                 for _ in range(2)]
-        frames.append(_sim(g, 100 + f, cysts=cysts)[0])
-    rf = torch.stack(frames).contiguous()
+    import sys
+    rf_all = simulate_training_frames(g, max(sizes), log=lambda m: print(m, file=sys.stderr, flush=True))
     torch.cuda.synchronize()
     t_sim = time.perf_counter() - t
-    model = LearnedApodization(g.n_el, seed=0)
-    t = time.perf_counter()
-    hist = model.train(rf, dg, args.steps, args.batch, args.lr, log_every=max(1, args.steps // 20))
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t
-    res = evaluate(model, g, dg, n_frames=args.eval_frames)
-    if args.save:
-        np.savez(args.save, **model.net.params())
-    print(json.dumps({"train_frames": args.frames, "steps": args.steps, "batch": args.batch, "sim_s": t_sim,
-                      "train_s": t_train, "loss": hist, "eval": res}), flush=True)
+    runs = []
+    for n in sizes:
+        model = LearnedApodization(g.n_el, seed=0)
+        t = time.perf_counter()
+        hist = model.train(rf_all[:n], dg, args.steps, args.batch, args.lr, log_every=max(1, args.steps // 20))
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t
+        res = evaluate(model, g, dg, n_frames=args.eval_frames)
+        runs.append({"train_frames": n, "train_s": t_train, "final_loss": hist[-1][1], "eval": res})
+        print(json.dumps(runs[-1]), flush=True)
+        if args.save and n == sizes[-1]:
+            np.savez(args.save, **model.net.params())
+    out = {"workload": "linear 128 el, 64 tx x 4 lines, 4096 samples; MV L = 32, loading 1e-2",
+           "steps": args.steps, "batch": args.batch, "lr": args.lr, "sim_s": t_sim, "runs": runs}
+    if args.out:
+        with open(args.out, "w") as f:
+            json.dump(out, f, indent=1)
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -182,3 +182,30 @@ def test_weighted_sum_and_fallback(u):
     y = u.beamform_weighted(torch.as_tensor(x).cuda(), torch.as_tensor(w).cuda(), torch.as_tensor(fb).cuda())
     ref = an.apply_weights(w, x, fb)
     np.testing.assert_allclose(y.cpu().numpy(), ref, rtol=1e-5, atol=1e-5)
+
+
+@pytest.mark.parametrize("m", [128, 96, 256, 32])
+def test_apply_is_forward_then_weighted_sum(u, m):
+    """usbf_apodnet_apply (network and weighted sum in one pass) against the two separate
+    calls and against float64 sums of its own weights (the network itself is checked against
+    the oracle above); a non-finite output bias sends every pixel to the fallback."""
+    params = an.init_params(7)
+    params["b4"][:] = 0.01
+    x = data(333, m, seed=9)
+    xt = torch.as_tensor(x).cuda()
+    fb = torch.arange(333, dtype=torch.float32, device="cuda")
+    net = u.ApodNet(params)
+    w_sep = net.forward(xt)
+    y_sep = u.beamform_weighted(xt, w_sep, fb)
+    w_out = torch.empty_like(xt)
+    y = net.apply(xt, fb, w_out=w_out)
+    assert torch.equal(w_out, w_sep)
+    assert (y - y_sep).abs().max().item() <= 1e-5 * y_sep.abs().max().item()
+    # the fused sum against float64 sums of the same weights, within binary32 summation error
+    wn = w_out.cpu().numpy().astype(np.float64)
+    y64 = an.apply_weights(wn, x)
+    scale = np.sum(np.abs(wn) * np.abs(x), axis=1)
+    assert np.all(np.abs(y.cpu().numpy() - y64) <= 1e-6 * scale + 1e-30)
+    params["b4"][:] = np.inf
+    y_bad = u.ApodNet(params).apply(xt, fb)
+    assert torch.equal(y_bad, fb)

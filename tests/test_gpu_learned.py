@@ -69,6 +69,7 @@ def test_evaluation_runs_and_reports(setup):
     # minimum variance narrows the point-spread function of delay and sum
     assert res["mv"]["psf_width_mm_mean"] < res["das"]["psf_width_mm_mean"]
     assert isinstance(res["learned_vs_mv"]["pass"], bool)
+    assert res["timing"]["mv_ms_per_frame"] > 0 and res["timing"]["learned_ms_per_frame"] > 0
 
 
 def test_fallback_on_non_finite_weights(setup):
