@@ -86,7 +86,7 @@ struct Shape {
   static constexpr int EC0 = buffer_bytes(G, FS) / (SPAN * FS * 4);
   static constexpr int EC = EC0 < max_chunk(FS) ? (EC0 < 1 ? 1 : EC0) : max_chunk(FS);
   static constexpr int BUFV = EC * SPAN;  // staging buffer length in frame vectors
-  static constexpr int BSTRIDE = BUFV + 1; // buffer pitch: each buffer ends in a zero vector
+  static constexpr int BSTRIDE = BUFV + 2; // buffer pitch: each buffer ends in two zero vectors
   static constexpr int IPT = (EC * (SPAN / 4) + kDasThreads - 1) / kDasThreads;
 };
 
@@ -98,7 +98,7 @@ struct Shape {
 // depths read taps depth_step = 2 samples apart, so their reads are consecutive in LDS.
 template <int G, int FS>
 struct TileLds {
-  typename FVec<FS>::T* win;  // [2][BUFV + 1]: window data, then one all-zero frame vector
+  typename FVec<FS>::T* win;  // [2][BUFV + 2]: window data, then two all-zero frame vectors
   float2* geo;                // [G][n_el]: (A, B) of the receive path
   float2* exy;                // [n_el]: element x, y (lateral offsets are taken from the lines)
   LineGeom* lines;            // [G]
@@ -107,9 +107,10 @@ struct TileLds {
   int* flg;                   // [(n_el + 3) / 4]: the flags, a byte per element, while they are built
 };
 
-// two staging buffers, each followed by an all-zero frame vector (kept zero for the whole
-// kernel): taps that contribute nothing read it, at the same offset in either buffer, so the
-// accumulation needs neither a branch nor a per-buffer select
+// two staging buffers, each followed by two all-zero frame vectors (kept zero for the whole
+// kernel): taps that contribute nothing read them, at the same offset in either buffer, so the
+// accumulation needs neither a branch nor a per-buffer select (and an unsplit window's two
+// neighbouring samples are always read from consecutive vectors)
 template <int G, int FS>
 __host__ __device__ constexpr size_t window_bytes() {
   return 2 * size_t(Shape<G, FS>::BSTRIDE) * FS * sizeof(float);
@@ -163,20 +164,40 @@ struct Items {
   int dst[IPT];
 };
 
-template <bool VEC, int G, int FS, int IPT>
-__device__ inline Items<IPT> chunk_items(const TileLds<G, FS>& t, const TileArgs& ta, const DasArgs& a, int c) {
-  Items<IPT> d;
+// The lane's staging items of a chunk: item threadIdx.x + it * kDasThreads is quad q of the
+// chunk's element k; the decomposition depends only on the lane and the window length, so it
+// is computed once per tile.
+template <int IPT>
+struct ItemSlots {
+  int k[IPT], q[IPT];
+};
+
+template <int IPT>
+__device__ inline ItemSlots<IPT> item_slots(const TileArgs& ta) {
+  ItemSlots<IPT> s;
   const int quads = ta.span >> 2;
+#pragma unroll
+  for (int it = 0; it < IPT; ++it) {
+    const int item = threadIdx.x + it * kDasThreads;
+    s.k[it] = item / quads;
+    s.q[it] = item - s.k[it] * quads;
+  }
+  return s;
+}
+
+template <bool VEC, int G, int FS, int IPT>
+__device__ inline Items<IPT> chunk_items(const TileLds<G, FS>& t, const TileArgs& ta, const DasArgs& a,
+                                         const ItemSlots<IPT>& sl, int c) {
+  Items<IPT> d;
   const int e0 = c * ta.ec;
   const int ec = min(ta.ec, a.n_el - e0);
   const int S = a.n_samples;
 #pragma unroll
   for (int it = 0; it < IPT; ++it) {
-    const int item = threadIdx.x + it * kDasThreads;
-    const int k = item / quads, q = item - k * quads, e = e0 + k;
+    const int k = sl.k[it], q = sl.q[it], e = e0 + k;
     d.voff[it] = 0u;
     d.dst[it] = -1;
-    if (item >= ec * quads || c < 0) continue;
+    if (k >= ec || c < 0) continue;
     const int2 wd = t.wnd[e];
     const int i = (wd.x & ~3) + 4 * q;
     if (!(wd.x & 2) || i > wd.y) continue;
@@ -323,7 +344,9 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
 #pragma unroll
     for (int f = 0; f < FS; ++f) FVec<FS>::set(z, f, 0.0f);
     t.win[ZERO] = z;
+    t.win[ZERO + 1] = z;
     t.win[SH::BSTRIDE + ZERO] = z;
+    t.win[SH::BSTRIDE + ZERO + 1] = z;
   }
   for (int e = tid; e < a.n_el; e += kDasThreads) {
     t.wnd[e] = make_int2(INT_MAX, INT_MIN);
@@ -411,6 +434,7 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
   static_assert(NS == 1 || NS % 2 == 0, "stages per chunk must be 1 or even");
   Prefetch<VEC, FS, IPT> pf[2];
   const bool stage_any = t_grp >= 0;
+  const ItemSlots<IPT> slots = item_slots<IPT>(ta);
 
   struct Taps {
     int off0[SH::EC], off1[SH::EC];
@@ -488,7 +512,7 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
     for (int f = 0; f < FB; ++f) acc[f] = 0.0f;
     float den = 0.0f;
     int c = next_chunk(-1);
-    Items<IPT> items = chunk_items<VEC, G, FS, IPT>(t, ta, a, c < n_chunks && stage_any ? c : -1);
+    Items<IPT> items = chunk_items<VEC, G, FS, IPT>(t, ta, a, slots, c < n_chunks && stage_any ? c : -1);
     // sum one stage (frames s FS .. s FS + FS - 1 of the block) from LDS buffer `buf`
     auto sum_stage = [&](const Taps& T, int buf, auto s_) {
       constexpr int s = decltype(s_)::value;
@@ -497,7 +521,7 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
       for (int k = 0; k < SH::EC; ++k) {
         // the zero vector sits after both buffers: index relative to this buffer
         const V x0 = *reinterpret_cast<const V*>(w + T.off0[k]);
-        const V x1 = *reinterpret_cast<const V*>(w + T.off1[k]);
+        const V x1 = *reinterpret_cast<const V*>(w + (FS > 1 ? T.off1[k] : T.off0[k] + int(sizeof(V))));
 #pragma unroll
         for (int f = 0; f < FS; ++f)
           acc[s * FS + f] = __builtin_fmaf(T.w0[k], FVec<FS>::get(x0, f),
@@ -511,7 +535,7 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
 
     if constexpr (NS == 1) {
       int cn = c < n_chunks ? next_chunk(c) : n_chunks;
-      Items<IPT> items_n = chunk_items<VEC, G, FS, IPT>(t, ta, a, cn < n_chunks && stage_any ? cn : -1);
+      Items<IPT> items_n = chunk_items<VEC, G, FS, IPT>(t, ta, a, slots, cn < n_chunks && stage_any ? cn : -1);
       issue_stage<VEC, FS, IPT>(pf[0], items, rsrc, 0u, fbytes, S);
       store_stage<VEC, G, FS, IPT>(pf[0], items, t.win, ta.span, ta.pshift);
       issue_stage<VEC, FS, IPT>(pf[1], items_n, rsrc, 0u, fbytes, S);
@@ -521,7 +545,7 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
         constexpr int P = decltype(P_)::value;
         const int cnn = cn < n_chunks ? next_chunk(cn) : n_chunks;
         const Items<IPT> items_nn =
-            chunk_items<VEC, G, FS, IPT>(t, ta, a, cnn < n_chunks && stage_any ? cnn : -1);
+            chunk_items<VEC, G, FS, IPT>(t, ta, a, slots, cnn < n_chunks && stage_any ? cnn : -1);
         if (cnn < n_chunks && stage_any) issue_stage<VEC, FS, IPT>(pf[P], items_nn, rsrc, 0u, fbytes, S);
         const Taps T = make_taps(c, den);
         // keep the scheduler from interleaving the tap set-up with the sums (it would hoist
@@ -550,7 +574,7 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
       while (c < n_chunks) {
         const int cn = next_chunk(c);
         const Items<IPT> next_items =
-            chunk_items<VEC, G, FS, IPT>(t, ta, a, cn < n_chunks && stage_any ? cn : -1);
+            chunk_items<VEC, G, FS, IPT>(t, ta, a, slots, cn < n_chunks && stage_any ? cn : -1);
         const Taps T = make_taps(c, den);
         __builtin_amdgcn_sched_barrier(0);
         auto step = [&](auto s_) {

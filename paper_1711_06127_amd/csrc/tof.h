@@ -145,27 +145,32 @@ __device__ inline Tap delay_tap(const DasArgs& a, int32_t b, float dtx, float dr
 }
 
 // The same tap, computed with the hardware square root and reciprocal (each within 1 ulp)
-// instead of the correctly rounded ones.  Let u = 2^-24.  The fast receive delay differs from
-// the rule's by at most 9u relative (3u for the rule's sqrt/add/divide, 6u for the fast
-// sqrt/add/reciprocal/multiply), and the three further roundings of dtx + drx, K (.) and
-// - T0 add at most 2u of each intermediate, so
-//   |dt_fast - dt_rule| <= u (10 K|drx| + 4 K|dtx + drx| + 2 |dt|)     (first order).
-// Twice that bound is used as a guard band: outside it floor(dt_fast) = floor(dt_rule) and the
-// fast value is kept (phi then differs from the rule's by less than the band); inside it the
-// rule itself is evaluated.  The integer index is therefore always the rule's.
+// instead of the correctly rounded ones, and with the constant part of the delay folded into
+// one fused multiply-add: d = fma(K, drx, K dtx - T0).  q and X are formed exactly as the rule
+// forms them, so their rounding is common to both.  With u = 2^-24 and first-order terms:
+//   |drx_fast - drx_rule| <= 9 u |drx|   (3u for the rule's sqrt/add/divide, 6u for the fast
+//                                         sqrt/add/reciprocal/multiply)
+//   rule, after drx       <= u (2 K |D| + |d|)          (D = dtx + drx, d = K D - T0)
+//   fast, after drx       <= u (2 K |dtx| + |T0| + |d|)
+// so |d_fast - d_rule| <= u (K (13 |drx| + 6 |dtx|) + 3 |T0|).  Twice that is the guard band:
+// outside it floor(d_fast) = floor(d_rule) and the fast value is kept (the fraction then
+// differs from the rule's by less than the band); inside it -- or where the fast value is not
+// finite (r = 0 and the element on the line's origin) -- the rule itself is evaluated.  The
+// integer index is therefore always the rule's.
 __device__ inline Tap fast_tap(const DasArgs& a, int32_t b, float dtx, float A, float B, float r, float r2,
                                float rr) {
   const float q = A - r2 * B;
   float X = q + rr;
   X = (X > 0.0f) ? X : 0.0f;
   const float s = __builtin_amdgcn_sqrtf(X) + r;
-  const float drx = (s > 0.0f) ? q * __builtin_amdgcn_rcpf(s) : 0.0f;
-  const float D = dtx + drx;
-  const float KD = a.K * D;
-  const float d = KD - a.T0;
+  const float drx = q * __builtin_amdgcn_rcpf(s);
+  const float c = a.K * dtx - a.T0;  // per pixel (hoisted out of element loops)
+  const float d = __builtin_fmaf(a.K, drx, c);
+  constexpr float u = 5.9604645e-08f;  // 2^-24
+  const float base = u * (12.0f * fabsf(a.K * dtx) + 6.0f * fabsf(a.T0)) + 1e-30f;  // per pixel
+  const float eps = __builtin_fmaf(26.0f * u * a.K, fabsf(drx), base);
   const float fl = floorf(d);
   const float fr = d - fl;
-  const float eps = 1.1920929e-07f * (20.0f * fabsf(a.K * drx) + 8.0f * fabsf(KD) + 4.0f * fabsf(d)) + 1e-30f;
   Tap t;
   if (fr > eps && fr < 1.0f - eps) {
     t.phi = fr;
@@ -175,10 +180,11 @@ __device__ inline Tap fast_tap(const DasArgs& a, int32_t b, float dtx, float A, 
   return delay_tap(a, b, dtx, small_rx_delay(A, B, r, r2, rr));
 }
 
+// F2 |dx| <= r (and F2 |dy| <= r): one product of the larger offset, which rounds to the larger
+// of the two products (rounding is monotonic), so the decision is the rule's.
 __device__ inline bool in_aperture(float F2, int array_dims, const ElemGeom& E, float r) {
-  bool act = F2 * fabsf(E.dx) <= r;
-  if (array_dims == 2) act = act && (F2 * fabsf(E.dy) <= r);
-  return act;
+  const float m = array_dims == 2 ? fmaxf(fabsf(E.dx), fabsf(E.dy)) : fabsf(E.dx);
+  return F2 * m <= r;
 }
 
 __device__ inline bool in_aperture(const DasArgs& a, const ElemGeom& E, float r) {
