@@ -203,6 +203,8 @@ def main():
                     help="no GPU: turn two rocprofv3 counter collections (FETCH_SIZE, WRITE_SIZE) of a "
                          "--calib-copy run into profiles/traffic.json")
     ap.add_argument("--traffic-command", default="", help="the profiled command, recorded with the figures")
+    ap.add_argument("--no-volume", action="store_true",
+                    help="skip the 3D volume measurement that the default (multi-line) run adds to its line")
     args = ap.parse_args()
     if args.traffic_from:
         return write_traffic(args)
@@ -221,11 +223,57 @@ def main():
     u.lib()
     if args.workload == "stream":
         return run_stream(args, dev)
-    builder, default_frames, desc = WORKLOADS[args.workload]
+    result = measure(args, args.workload, dev)
+    if args.workload == "multiline" and not args.no_volume and args.apod_sets == 1:
+        # the volume rate of the 3D workload beside the headline 2D figure
+        vargs = argparse.Namespace(**vars(args))
+        vargs.frames, vargs.streams, vargs.unordered, vargs.envelope = 1, 1, False, "hilbert"
+        vargs.steps, vargs.warmup = max(3, min(args.steps, 10)), 2
+        vargs.calib_copy = False
+        v = measure(vargs, "volume", dev, cpu_stages=not args.no_cpu)
+        result["volume"] = {"workload": v["config"]["workload"], "volumes_per_s": v["frames_per_s"],
+                            "ms_per_volume": v["ms_per_step"], "steps": v["steps"], "stage_ms": v["stage_ms"],
+                            "pixel_channel_samples_per_s": v["value"], "roofline": v["roofline"],
+                            "cpu_stages_s": v.get("cpu_stages_s")}
+    print(json.dumps(result), flush=True)
+
+
+def cpu_stage_times(g, rf_host):
+    """The oracle's time per stage on the first frame (volume) of the batch: delay and sum,
+    envelope, log compression, scan conversion."""
+    import oracle
+    t = time.perf_counter()
+    y = oracle.das(g, rf_host[:1])[0]
+    t_das = time.perf_counter() - t
+    t = time.perf_counter()
+    env = oracle.envelope(y)
+    t_env = time.perf_counter() - t
+    t = time.perf_counter()
+    b = oracle.log_compress(env, 50.0)
+    t_log = time.perf_counter() - t
+    t = time.perf_counter()
+    if g.scan.kind == 1:
+        oracle.scan_convert_3d(b, g.scan)
+    else:
+        oracle.scan_convert_2d(b, g.scan)
+    t_scan = time.perf_counter() - t
+    return {"das": t_das, "envelope": t_env, "log_compress": t_log, "scan_convert": t_scan,
+            "cores": oracle.num_threads(), "kind": "oracle"}
+
+
+def measure(args, workload, dev, cpu_stages=False):
+    """Times `workload` per the arguments; returns the result dict of the bench line."""
+    import numpy as np
+    import torch
+
+    import paper_1711_06127_amd as u
+    import synth
+
+    builder, default_frames, desc = WORKLOADS[workload]
     g = getattr(synth, builder)()
     F = args.frames or default_frames
     t = time.perf_counter()
-    rf = make_batch(g, F, min(args.unique_frames, F), dev, volume=args.workload == "volume")
+    rf = make_batch(g, F, min(args.unique_frames, F), dev, volume=workload == "volume")
     torch.cuda.synchronize()
     log(f"inputs: {tuple(rf.shape)} int16 ({rf.numel() * 2 / 2**30:.2f} GiB) generated in {time.perf_counter() - t:.1f} s")
     dg = u.DeviceGeometry(g, dev)
@@ -360,10 +408,14 @@ def main():
         torch.cuda.synchronize()
         torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
-    if not args.no_cpu:
+    if cpu_stages:
+        result["cpu_stages_s"] = cpu_stage_times(g, rf[:1].cpu().numpy())
+    elif not args.no_cpu:
         rf_h = rf.cpu().numpy()
         result["cpu_baseline"] = cpu_baseline(g, rf_h, args.cpu_budget)
-    print(json.dumps(result), flush=True)
+    del rf
+    torch.cuda.empty_cache()
+    return result
 
 
 def run_stream(args, dev):

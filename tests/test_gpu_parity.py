@@ -98,6 +98,21 @@ def test_beamform_multiline_frames(usbf, n_frames):
     assert rel_err(got, ref) <= TOL
 
 
+def test_beamform_32_frame_launch_first_and_last_frames_whole(usbf):
+    """The benchmark's launch -- 32 multi-line frames in one block -- with the first and the last
+    frame compared element by element (256 x 2048 lines each) against the oracle."""
+    g = synth.config_multiline_2d()
+    base = sim(g, 2600, n_frames=2)
+    rf = base[torch.arange(32) % 2].clone()
+    rf[2:] = torch.roll(rf[2:], shifts=5, dims=-1)
+    rf[31] = torch.flip(rf[31], dims=[-1])  # the last frame unlike every other
+    dg = usbf.DeviceGeometry(g)
+    y = usbf.beamform(rf, dg).cpu().numpy()
+    ref = oracle.das(g, rf[[0, 31]].cpu().numpy())
+    for k, f in enumerate((0, 31)):
+        assert rel_err(y[f], ref[k]) <= TOL, f
+
+
 def test_beamform_small_geometry_frame_blocks(usbf):
     """One line per transmit with 37 frames (blocks of 32 + 4 + 1) against the oracle on
     sampled pixels of every frame."""
@@ -140,6 +155,23 @@ def test_beamform_full_volume_sampled(usbf):
     pix = np.stack([np.zeros(m, np.int64), rng.integers(0, g.n_lines, m), rng.integers(0, g.n_depth, m)], 1)
     ref = oracle.das(g, rf.cpu().numpy(), pix)
     assert rel_err(y[pix[:, 0], pix[:, 1], pix[:, 2]], ref) <= TOL
+
+
+def test_beamform_full_volume_depth_rows_every_line(usbf):
+    """The whole 3D workload in the benchmark's launch: eight depth rows (both ends, the
+    quarter points, a row inside each of the first and last depth tiles) of every one of the
+    1024 lines, element by element against the oracle."""
+    g = synth.config_volume_3d()
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(12)
+    rf = torch.randint(-3000, 3000, (1, g.n_tx, g.n_el, g.n_samples), dtype=torch.int16, device="cuda", generator=gen)
+    dg = usbf.DeviceGeometry(g)
+    y = usbf.beamform(rf, dg).cpu().numpy()[0]
+    rows = np.array([0, 1, 200, 250, 500, 750, 900, g.n_depth - 1])
+    pix = np.stack([np.zeros(g.n_lines * rows.size, np.int64), np.repeat(np.arange(g.n_lines), rows.size),
+                    np.tile(rows, g.n_lines)], 1)
+    ref = oracle.das(g, rf.cpu().numpy(), pix)
+    assert rel_err(y[pix[:, 1], pix[:, 2]], ref) <= TOL
 
 
 def test_beamform_edge_cases(usbf):
