@@ -76,6 +76,17 @@ struct FVec<4> {
   __device__ static void set(T& v, int f, float x) { (f == 0 ? v.x : f == 1 ? v.y : f == 2 ? v.z : v.w) = x; }
 };
 
+// Element type of a staged window: single-frame windows keep the int16 samples as they are
+// (the sum converts its two taps), multi-frame windows hold binary32 vectors of FS frames.
+template <int FS>
+struct WinT {
+  using T = typename FVec<FS>::T;
+};
+template <>
+struct WinT<1> {
+  using T = int16_t;
+};
+
 // Compile-time shape of a tile: G lines x TD depths; a window of SPAN samples per element for
 // depth_step <= 2; EC elements per chunk so that one staging buffer fits buffer_bytes(G, FS); IPT
 // staging items (4 samples x FS frames) per lane.
@@ -83,10 +94,12 @@ template <int G, int FS>
 struct Shape {
   static constexpr int TD = kDasThreads / G;
   static constexpr int SPAN = 2 * TD + kWindowMargin;
-  static constexpr int EC0 = buffer_bytes(G, FS) / (SPAN * FS * 4);
+  static constexpr int EC0 = buffer_bytes(G, FS) / (SPAN * int(sizeof(typename WinT<FS>::T)));
   static constexpr int EC = EC0 < max_chunk(FS) ? (EC0 < 1 ? 1 : EC0) : max_chunk(FS);
-  static constexpr int BUFV = EC * SPAN;  // staging buffer length in frame vectors
-  static constexpr int BSTRIDE = BUFV + 2; // buffer pitch: each buffer ends in two zero vectors
+  static constexpr int BUFV = EC * SPAN;  // staging buffer length in window elements
+  // buffer pitch: each buffer ends in two zero vectors (four zero samples for int16 windows,
+  // which keeps the second buffer 8-byte aligned)
+  static constexpr int BSTRIDE = BUFV + (FS == 1 ? 4 : 2);
   static constexpr int IPT = (EC * (SPAN / 4) + kDasThreads - 1) / kDasThreads;
 };
 
@@ -98,7 +111,7 @@ struct Shape {
 // depths read taps depth_step = 2 samples apart, so their reads are consecutive in LDS.
 template <int G, int FS>
 struct TileLds {
-  typename FVec<FS>::T* win;  // [2][BUFV + 2]: window data, then two all-zero frame vectors
+  typename WinT<FS>::T* win;  // [2][BSTRIDE]: window data, then all-zero vectors
   float2* geo;                // [G][n_el]: (A, B) of the receive path
   float2* exy;                // [n_el]: element x, y (lateral offsets are taken from the lines)
   LineGeom* lines;            // [G]
@@ -113,7 +126,7 @@ struct TileLds {
 // neighbouring samples are always read from consecutive vectors)
 template <int G, int FS>
 __host__ __device__ constexpr size_t window_bytes() {
-  return 2 * size_t(Shape<G, FS>::BSTRIDE) * FS * sizeof(float);
+  return 2 * size_t(Shape<G, FS>::BSTRIDE) * sizeof(typename WinT<FS>::T);
 }
 
 template <int G, int FS>
@@ -124,9 +137,8 @@ __host__ __device__ inline size_t tile_lds_bytes(int n_el) {
 
 template <int G, int FS>
 __device__ inline TileLds<G, FS> carve(unsigned char* base, int n_el) {
-  using V = typename FVec<FS>::T;
   TileLds<G, FS> t;
-  t.win = reinterpret_cast<V*>(base);
+  t.win = reinterpret_cast<typename WinT<FS>::T*>(base);
   t.geo = reinterpret_cast<float2*>(base + window_bytes<G, FS>());
   t.exy = t.geo + size_t(G) * n_el;
   t.lines = reinterpret_cast<LineGeom*>(t.exy + n_el);
@@ -169,18 +181,24 @@ struct Items {
 // is computed once per tile.
 template <int IPT>
 struct ItemSlots {
-  int k[IPT], q[IPT];
+  int k[IPT];      // element of the chunk
+  int q4[IPT];     // first sample of the quad within the window
+  int kS[IPT];     // k * n_samples: the element's record relative to the chunk's first
+  int dst[IPT];    // window-relative LDS index of the quad's first sample
 };
 
-template <int IPT>
-__device__ inline ItemSlots<IPT> item_slots(const TileArgs& ta) {
+template <int IPT, int FS>
+__device__ inline ItemSlots<IPT> item_slots(const TileArgs& ta, int S) {
   ItemSlots<IPT> s;
   const int quads = ta.span >> 2;
 #pragma unroll
   for (int it = 0; it < IPT; ++it) {
     const int item = threadIdx.x + it * kDasThreads;
-    s.k[it] = item / quads;
-    s.q[it] = item - s.k[it] * quads;
+    const int k = item / quads, q = item - k * quads;
+    s.k[it] = k;
+    s.q4[it] = 4 * q;
+    s.kS[it] = k * S;
+    s.dst[it] = k * ta.span + ((FS > 1 && ta.pshift) ? 2 * q : 4 * q);
   }
   return s;
 }
@@ -192,18 +210,23 @@ __device__ inline Items<IPT> chunk_items(const TileLds<G, FS>& t, const TileArgs
   const int e0 = c * ta.ec;
   const int ec = min(ta.ec, a.n_el - e0);
   const int S = a.n_samples;
+  const int e0S = e0 * S;
 #pragma unroll
   for (int it = 0; it < IPT; ++it) {
-    const int k = sl.k[it], q = sl.q[it], e = e0 + k;
+    const int k = sl.k[it], e = e0 + k;
     d.voff[it] = 0u;
     d.dst[it] = -1;
     if (k >= ec || c < 0) continue;
     const int2 wd = t.wnd[e];
-    const int i = (wd.x & ~3) + 4 * q;
+    const int i = (wd.x & ~3) + sl.q4[it];
     if (!(wd.x & 2) || i > wd.y) continue;
     uint32_t in = 0u;
+    if constexpr (VEC) {
+      in = (i >= 0 && i < S) ? 15u : 0u;  // S % 4 == 0 and i % 4 == 0: all four or none
+    } else {
 #pragma unroll
-    for (int s = 0; s < 4; ++s) in |= (i + s >= 0 && i + s < S) ? (1u << s) : 0u;
+      for (int s = 0; s < 4; ++s) in |= (i + s >= 0 && i + s < S) ? (1u << s) : 0u;
+    }
     // A quad with no sample inside the record loads (and then masks) the record's first
     // samples instead: windows reach past either end of the record for deep pixels at the edge
     // of the aperture.  Window starts are multiples of 4, so a quad that starts before the
@@ -211,8 +234,8 @@ __device__ inline Items<IPT> chunk_items(const TileLds<G, FS>& t, const TileArgs
     // and its samples beyond the end are clamped in issue_stage.  Every load therefore stays
     // inside element e's record.  (VEC: S % 4 == 0, all four inside or all outside.)
     const int ic = in ? i : 0;
-    d.voff[it] = uint32_t((size_t(e) * S + ic) * sizeof(int16_t));
-    d.dst[it] = (k * ta.span + ((FS > 1 && ta.pshift) ? 2 * q : 4 * q)) | int(in << 26);
+    d.voff[it] = uint32_t(e0S + sl.kS[it] + ic) * uint32_t(sizeof(int16_t));
+    d.dst[it] = sl.dst[it] | int(in << 26);
   }
   return d;
 }
@@ -258,7 +281,7 @@ __device__ inline void issue_stage(Prefetch<VEC, FS, IPT>& pf, const Items<IPT>&
 
 template <bool VEC, int G, int FS, int IPT>
 __device__ inline void store_stage(const Prefetch<VEC, FS, IPT>& pf, const Items<IPT>& it_,
-                                   typename FVec<FS>::T* win, int span, int pshift) {
+                                   typename WinT<FS>::T* win, int span, int pshift) {
   using V = typename FVec<FS>::T;
   const int half = span >> 1;
 #pragma unroll
@@ -268,26 +291,32 @@ __device__ inline void store_stage(const Prefetch<VEC, FS, IPT>& pf, const Items
     const uint32_t in = uint32_t(dst) >> 26;
     const uint32_t m0 = (in & 1u) ? 0xffffu : 0u, m1 = (in & 2u) ? 0xffff0000u : 0u;
     const uint32_t m2 = (in & 4u) ? 0xffffu : 0u, m3 = (in & 8u) ? 0xffff0000u : 0u;
-    V x[4];
-#pragma unroll
-    for (int f = 0; f < FS; ++f) {
-      const uint32_t dx = pf.d[it][f].x & (m0 | m1), dy = pf.d[it][f].y & (m2 | m3);
-      FVec<FS>::set(x[0], f, lo16(dx));
-      FVec<FS>::set(x[1], f, hi16(dx));
-      FVec<FS>::set(x[2], f, lo16(dy));
-      FVec<FS>::set(x[3], f, hi16(dy));
-    }
-    V* w = win + (dst & kDstMask);
-    if (FS > 1 && pshift) {
-      w[0] = x[0];
-      w[1] = x[2];
-      w[half] = x[1];
-      w[half + 1] = x[3];
+    if constexpr (FS == 1) {
+      // int16 window: the four samples as loaded, those outside the record cleared
+      *reinterpret_cast<uint2*>(win + (dst & kDstMask)) =
+          make_uint2(pf.d[it][0].x & (m0 | m1), pf.d[it][0].y & (m2 | m3));
     } else {
-      w[0] = x[0];
-      w[1] = x[1];
-      w[2] = x[2];
-      w[3] = x[3];
+      V x[4];
+#pragma unroll
+      for (int f = 0; f < FS; ++f) {
+        const uint32_t dx = pf.d[it][f].x & (m0 | m1), dy = pf.d[it][f].y & (m2 | m3);
+        FVec<FS>::set(x[0], f, lo16(dx));
+        FVec<FS>::set(x[1], f, hi16(dx));
+        FVec<FS>::set(x[2], f, lo16(dy));
+        FVec<FS>::set(x[3], f, hi16(dy));
+      }
+      V* w = win + (dst & kDstMask);
+      if (pshift) {
+        w[0] = x[0];
+        w[1] = x[2];
+        w[half] = x[1];
+        w[half + 1] = x[3];
+      } else {
+        w[0] = x[0];
+        w[1] = x[1];
+        w[2] = x[2];
+        w[3] = x[3];
+      }
     }
   }
 }
@@ -311,6 +340,7 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
                                          const TileArgs& ta, float* __restrict__ out, unsigned char* lds_raw,
                                          int group, int dt) {
   using V = typename FVec<FS>::T;
+  using W = typename WinT<FS>::T;
   using SH = Shape<G, FS>;
   constexpr int TD = SH::TD;
   constexpr int NS = FB / FS;
@@ -340,13 +370,16 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
     if (SETS) set_params(a, tid / gl, t.lines[tid]);
   }
   if (tid == 0) {
-    V z;
+    using W = typename WinT<FS>::T;
+    W z;
+    if constexpr (FS == 1) {
+      z = 0;
+    } else {
 #pragma unroll
-    for (int f = 0; f < FS; ++f) FVec<FS>::set(z, f, 0.0f);
-    t.win[ZERO] = z;
-    t.win[ZERO + 1] = z;
-    t.win[SH::BSTRIDE + ZERO] = z;
-    t.win[SH::BSTRIDE + ZERO + 1] = z;
+      for (int f = 0; f < FS; ++f) FVec<FS>::set(z, f, 0.0f);
+    }
+    for (int b = 0; b < 2; ++b)
+      for (int k = ZERO; k < SH::BSTRIDE; ++k) t.win[b * SH::BSTRIDE + k] = z;
   }
   for (int e = tid; e < a.n_el; e += kDasThreads) {
     t.wnd[e] = make_int2(INT_MAX, INT_MIN);
@@ -434,8 +467,10 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
   static_assert(NS == 1 || NS % 2 == 0, "stages per chunk must be 1 or even");
   Prefetch<VEC, FS, IPT> pf[2];
   const bool stage_any = t_grp >= 0;
-  const ItemSlots<IPT> slots = item_slots<IPT>(ta);
+  const ItemSlots<IPT> slots = item_slots<IPT, FS>(ta, S);
 
+  // the last y offset whose Hann factor was computed, and that factor (separable windows)
+  float hy_dy = __builtin_nanf(""), hy = 0.0f;
   struct Taps {
     int off0[SH::EC], off1[SH::EC];
     float w0[SH::EC], w1[SH::EC];
@@ -451,7 +486,7 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
     const int e0 = __builtin_amdgcn_readfirstlane(c * ta.ec);
 #pragma unroll
     for (int k = 0; k < SH::EC; ++k) {
-      T.off0[k] = T.off1[k] = ZERO * int(sizeof(V));
+      T.off0[k] = T.off1[k] = ZERO * int(sizeof(W));
       T.w0[k] = T.w1[k] = 0.0f;
       if (k >= ta.ec) continue;
       const int e = min(e0 + k, a.n_el - 1);
@@ -460,7 +495,22 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
       const ElemGeom E{E2.x, E2.y, xy.x - L.olx, xy.y - L.oly};
       const bool act = lane_ok && e0 + k < a.n_el && in_aperture(ap_F2, a.array_dims, E, r);
       if (!__any(act)) continue;  // no lane of the wave needs this element
-      const float w = act ? apod_weight(ap_window, a.array_dims, E.dx, E.dy, inv_w) : 0.0f;
+      float w = 0.0f;
+      if (act) {
+        if (ap_window == USBF_WINDOW_RECT) {
+          w = 1.0f;
+        } else if (a.array_dims == 2) {
+          // separable window: the y factor is kept while consecutive elements share their row
+          // (a wave-uniform branch: skipped unless some lane meets a new row)
+          if (__any(E.dy != hy_dy)) {
+            hy = hann(E.dy, inv_w);
+            hy_dy = E.dy;
+          }
+          w = hann(E.dx, inv_w) * hy;
+        } else {
+          w = hann(E.dx, inv_w);
+        }
+      }
       den += w;
       const Tap tp = fast_tap(a, b, dtx, E.A, E.B, r, r2, rr);
       const bool ok = act && tp.i0 >= 0 && tp.i0 <= S - 2;
@@ -475,8 +525,8 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
       const int p0 = split ? ((rel & 1) * half + (rel >> 1)) : rel;
       const int p1 = split ? (((rel + 1) & 1) * half + ((rel + 1) >> 1)) : rel + 1;
       // byte offsets within a buffer
-      T.off0[k] = ((ok && in_win) ? wbase + p0 : ZERO) * int(sizeof(V));
-      T.off1[k] = ((ok && in_win) ? wbase + p1 : ZERO) * int(sizeof(V));
+      T.off0[k] = ((ok && in_win) ? wbase + p0 : ZERO) * int(sizeof(W));
+      T.off1[k] = ((ok && in_win) ? wbase + p1 : ZERO) * int(sizeof(W));
       T.slow |= (ok && !in_win) ? (1u << k) : 0u;
     }
     return T;
@@ -520,12 +570,17 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
 #pragma unroll
       for (int k = 0; k < SH::EC; ++k) {
         // the zero vector sits after both buffers: index relative to this buffer
-        const V x0 = *reinterpret_cast<const V*>(w + T.off0[k]);
-        const V x1 = *reinterpret_cast<const V*>(w + (FS > 1 ? T.off1[k] : T.off0[k] + int(sizeof(V))));
+        if constexpr (FS == 1) {
+          const int16_t* p = reinterpret_cast<const int16_t*>(w + T.off0[k]);
+          acc[s] = __builtin_fmaf(T.w0[k], float(p[0]), __builtin_fmaf(T.w1[k], float(p[1]), acc[s]));
+        } else {
+          const V x0 = *reinterpret_cast<const V*>(w + T.off0[k]);
+          const V x1 = *reinterpret_cast<const V*>(w + T.off1[k]);
 #pragma unroll
-        for (int f = 0; f < FS; ++f)
-          acc[s * FS + f] = __builtin_fmaf(T.w0[k], FVec<FS>::get(x0, f),
-                                           __builtin_fmaf(T.w1[k], FVec<FS>::get(x1, f), acc[s * FS + f]));
+          for (int f = 0; f < FS; ++f)
+            acc[s * FS + f] = __builtin_fmaf(T.w0[k], FVec<FS>::get(x0, f),
+                                             __builtin_fmaf(T.w1[k], FVec<FS>::get(x1, f), acc[s * FS + f]));
+        }
       }
       // pin this stage's sums here: otherwise the accumulation may be sunk below later stages,
       // keeping every stage's LDS reads alive at once

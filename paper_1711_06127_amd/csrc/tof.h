@@ -193,12 +193,15 @@ __device__ inline bool in_aperture(const DasArgs& a, const ElemGeom& E, float r)
 
 #pragma clang fp contract(on)
 
+// Hann factor 1/2 + 1/2 cos(2 pi u) of an offset d at inv_w = f_number / r; the hardware
+// cosine takes its argument in revolutions.
+__device__ inline float hann(float d, float inv_w) { return 0.5f + 0.5f * __builtin_amdgcn_cosf(d * inv_w); }
+
 // Apodization weight (a value, not part of the index rule).  inv_w = f_number / r.
 __device__ inline float apod_weight(int window, int dims, float dx, float dy, float inv_w) {
   if (window == USBF_WINDOW_RECT) return 1.0f;
-  // Hann: 1/2 + 1/2 cos(2 pi u); the hardware cosine takes its argument in revolutions.
-  float w = 0.5f + 0.5f * __builtin_amdgcn_cosf(dx * inv_w);
-  if (dims == 2) w *= 0.5f + 0.5f * __builtin_amdgcn_cosf(dy * inv_w);
+  float w = hann(dx, inv_w);
+  if (dims == 2) w *= hann(dy, inv_w);
   return w;
 }
 
