@@ -155,8 +155,15 @@ __device__ inline void stage_c(const c32* __restrict__ a, c32* __restrict__ b, c
     for (int r = 0; r < R; ++r) v[r] = a[pad(j + r * M)];
     const int k = j % NS;
     if constexpr (NS > 1) {
+      // twiddles W^(r k TWS) as powers of W^(k TWS): one table read per butterfly
+      const c32 w1 = tw[pad(k * TWS)];
+      c32 w = w1;
+      v[1] = cmul(v[1], w);
 #pragma unroll
-      for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[pad(r * k * TWS)]);
+      for (int r = 2; r < R; ++r) {
+        w = cmul(w, w1);
+        v[r] = cmul(v[r], w);
+      }
     }
     if constexpr (R == 2) dft2(v);
     if constexpr (R == 4) dft4(v);
@@ -200,8 +207,15 @@ __device__ inline void stage_ls(const c32* __restrict__ tw, Load load, Store sto
     for (int r = 0; r < R; ++r) v[r] = load(j, r, M);
     const int k = j % NS;
     if constexpr (NS > 1) {
+      // twiddles W^(r k TWS) as powers of W^(k TWS): one table read per butterfly
+      const c32 w1 = tw[pad(k * TWS)];
+      c32 w = w1;
+      v[1] = cmul(v[1], w);
 #pragma unroll
-      for (int r = 1; r < R; ++r) v[r] = cmul(v[r], tw[pad(r * k * TWS)]);
+      for (int r = 2; r < R; ++r) {
+        w = cmul(w, w1);
+        v[r] = cmul(v[r], w);
+      }
     }
     if constexpr (R == 2) dft2(v);
     if constexpr (R == 4) dft4(v);
@@ -233,6 +247,24 @@ __host__ __device__ constexpr int last_src(int cur) {
   return (NS * radix_at<N, NS>() == N) ? cur : last_src<N, NS * radix_at<N, NS>()>(cur ^ 1);
 }
 
+// Largest twiddle index the power-of-two transform reads, (NS - 1) * N / (NS * R) over its
+// stages, plus one: the table holds W^0 .. W^(that - 1) only.
+template <int N, int NS = 1>
+__host__ __device__ constexpr int pow2_twiddles() {
+  if constexpr (NS >= N) {
+    return 1;
+  } else {
+    constexpr int R = radix_at<N, NS>();
+    constexpr int here = (NS - 1) * (N / (NS * R)) + 1;
+    constexpr int rest = pow2_twiddles<N, NS * R>();
+    return here > rest ? here : rest;
+  }
+}
+template <int N>
+__host__ __device__ constexpr size_t pow2_lds_bytes() {
+  return (size_t(2) * padded_len(N) + padded_len(pow2_twiddles<N>())) * sizeof(c32);
+}
+
 // in == env is allowed (the pipeline detects in place): every row is read whole before any
 // of it is written, and the prefetched next row is another row, so neither pointer is
 // declared restrict.
@@ -247,7 +279,7 @@ __global__ __launch_bounds__(kEnvThreads) void envelope_pow2_kernel(const float*
   c32* buf1 = lds + np;
   c32* tw = lds + 2 * np;
   const int tid = threadIdx.x;
-  for (int k = tid; k < N; k += kEnvThreads) {
+  for (int k = tid; k < pow2_twiddles<N>(); k += kEnvThreads) {
     float s, c;
     sincospif(2.0f * float(k) / float(N), &s, &c);
     tw[pad(k)] = {c, -s};
@@ -503,7 +535,11 @@ int envelope_enqueue(const float* in, int64_t n_rows, int n, float* env, float* 
   // holds 160 KB / (24 n) workgroups
   int dev = 0, n_cu = 256;
   if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
-  const size_t lds = size_t(3) * padded_len(n) * sizeof(c32);
+  size_t lds = size_t(3) * padded_len(n) * sizeof(c32);
+  if (n == 2048) lds = pow2_lds_bytes<2048>();
+  if (n == 1024) lds = pow2_lds_bytes<1024>();
+  if (n == 512) lds = pow2_lds_bytes<512>();
+  if (n == 256) lds = pow2_lds_bytes<256>();
   const int per_cu = std::max(1, std::min(8, int(163840 / (lds + 64))));
   const int64_t blocks = std::min<int64_t>(n_rows, int64_t(n_cu) * per_cu);
   bool primes = false;
