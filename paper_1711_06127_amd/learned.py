@@ -320,9 +320,15 @@ def main():
     ap.add_argument("--eval-frames", type=int, default=32)
     ap.add_argument("--save", default="")
     ap.add_argument("--out", default="", help="also write the result JSON to this file")
+    ap.add_argument("--timing-only", action="store_true",
+                    help="only time the two adaptive paths on one held-out frame (untrained network)")
     args = ap.parse_args()
     g = synth.config_multiline_2d()
     dg = DeviceGeometry(g)
+    if args.timing_only:
+        rf, _, _ = eval_phantom(g, 90000)
+        print(json.dumps({"timing": time_paths(LearnedApodization(g.n_el, seed=0), rf, dg)}), flush=True)
+        return
     sizes = [int(v) for v in args.frames.split(",")]
     t = time.perf_counter()
     import sys
