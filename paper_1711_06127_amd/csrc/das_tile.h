@@ -38,7 +38,7 @@ constexpr int kDasThreads = 256;
 #define USBF_DAS_BUF_SINGLE 78336
 #endif
 #ifndef USBF_DAS_BUF_FRAME
-#define USBF_DAS_BUF_FRAME 6528
+#define USBF_DAS_BUF_FRAME 5448
 #endif
 #ifndef USBF_DAS_MAX_CHUNK
 #define USBF_DAS_MAX_CHUNK 12
@@ -103,6 +103,34 @@ struct Shape {
   static constexpr int IPT = (EC * (SPAN / 4) + kDasThreads - 1) / kDasThreads;
 };
 
+// Tiles of one line and one frame (3D volumes, single-line frames): every lane of the workgroup
+// beamforms the same line, so everything about an element except the depth is the same for all
+// lanes.  For each chunk the workgroup tabulates those element constants once, next to the
+// chunk's staging buffer, and the lanes read them with two broadcast LDS reads per element
+// instead of re-deriving them per pixel.
+template <int G, int FS, bool SETS = false>
+__host__ __device__ constexpr bool one_line_tile() {
+  return G == 1 && FS == 1 && !SETS;
+}
+
+struct alignas(16) ChunkTap {
+  float A, B;  // receive constants of the line (ElemGeom)
+  float dx;    // lateral x offset (Hann factor)
+  float dy;    // lateral y offset
+  float thr;   // F2 times the lateral offset the aperture tests: inside iff thr <= r
+  int cb;      // taps i0 in [lo, lo + rng] are summed from the staged window, whose sample lo
+  int lo;      // sits at byte cb of the buffer (lo = n_samples, rng = 0 and cb = the zero vector
+  int rng;     // when nothing is staged: that tap is outside the record)
+};
+
+// after a chunk's table: its elements' lateral y offsets if there are at most two of them
+struct alignas(16) ChunkHdr {
+  float dyA, dyB;
+  int two;  // every element's y offset is dyA or dyB
+  int pad;
+};
+static_assert(sizeof(ChunkHdr) <= sizeof(ChunkTap), "the header takes one table entry");
+
 // LDS of one workgroup: two staging buffers, the per-(line, element) receive constants of the
 // G lines, their LineGeom, and per element the tap window [lo, hi] and flags.
 // A staged window holds the samples of one element for FS frames; with pshift = 1 (and FS > 1:
@@ -112,6 +140,8 @@ struct Shape {
 template <int G, int FS>
 struct TileLds {
   typename WinT<FS>::T* win;  // [2][BSTRIDE]: window data, then all-zero vectors
+  ChunkTap* ctab;             // [2][EC + 1], one-line tiles only: element constants of each buffer's
+                              // chunk, then its header (ChunkHdr)
   float2* geo;                // [G][n_el]: (A, B) of the receive path
   float2* exy;                // [n_el]: element x, y (lateral offsets are taken from the lines)
   LineGeom* lines;            // [G]
@@ -130,18 +160,32 @@ __host__ __device__ constexpr size_t window_bytes() {
 }
 
 template <int G, int FS>
+__host__ __device__ constexpr size_t ctab_bytes() {
+  return one_line_tile<G, FS>() ? 2 * size_t(Shape<G, FS>::EC + 1) * sizeof(ChunkTap) : 0;
+}
+
+// per-(line, element) receive constants and element positions (one-line tiles derive them from
+// the geometry arrays when they tabulate a chunk instead)
+template <int G, int FS>
+__host__ __device__ constexpr size_t geo_entries(int n_el) {
+  return one_line_tile<G, FS>() ? 0 : size_t(G + 1) * n_el;
+}
+
+template <int G, int FS>
 __host__ __device__ inline size_t tile_lds_bytes(int n_el) {
-  return window_bytes<G, FS>() + size_t(G + 1) * n_el * sizeof(float2) + G * sizeof(LineGeom) +
-         size_t(n_el) * sizeof(int2) + size_t((n_el + 3) / 4) * sizeof(int);
+  return window_bytes<G, FS>() + ctab_bytes<G, FS>() + geo_entries<G, FS>(n_el) * sizeof(float2) +
+         G * sizeof(LineGeom) + size_t(n_el) * sizeof(int2) + size_t((n_el + 3) / 4) * sizeof(int);
 }
 
 template <int G, int FS>
 __device__ inline TileLds<G, FS> carve(unsigned char* base, int n_el) {
+  static_assert(window_bytes<G, FS>() % 16 == 0, "the tap table after the buffers needs 16-byte alignment");
   TileLds<G, FS> t;
   t.win = reinterpret_cast<typename WinT<FS>::T*>(base);
-  t.geo = reinterpret_cast<float2*>(base + window_bytes<G, FS>());
-  t.exy = t.geo + size_t(G) * n_el;
-  t.lines = reinterpret_cast<LineGeom*>(t.exy + n_el);
+  t.ctab = reinterpret_cast<ChunkTap*>(base + window_bytes<G, FS>());
+  t.geo = reinterpret_cast<float2*>(base + window_bytes<G, FS>() + ctab_bytes<G, FS>());
+  t.exy = t.geo + size_t(G) * n_el;  // (neither table exists in one-line tiles)
+  t.lines = reinterpret_cast<LineGeom*>(t.geo + geo_entries<G, FS>(n_el));
   t.wnd = reinterpret_cast<int2*>(t.lines + G);
   t.flg = reinterpret_cast<int*>(t.wnd + n_el);
   return t;
@@ -166,9 +210,10 @@ __device__ inline float hi16(uint32_t d) { return float(int16_t(d >> 16)); }
 
 // One staging item: four consecutive samples of one element's window.  `voff` is the byte
 // offset of the first sample within the transmit's block of a frame (clamped into the
-// record); `dst` the window-relative LDS index of the first sample, with bits 26..29 saying
-// which of the four samples are inside the record; dst < 0: nothing to stage.
-constexpr int kDstMask = (1 << 26) - 1;
+// record); `dst` the window-relative LDS index of the first sample; dst < 0: nothing to stage.
+// Window samples outside the record are staged as whatever the clamped load returns: a tap is
+// summed from the window only when both of its samples lie inside the record, so they are
+// never read.
 
 template <int IPT>
 struct Items {
@@ -220,22 +265,15 @@ __device__ inline Items<IPT> chunk_items(const TileLds<G, FS>& t, const TileArgs
     const int2 wd = t.wnd[e];
     const int i = (wd.x & ~3) + sl.q4[it];
     if (!(wd.x & 2) || i > wd.y) continue;
-    uint32_t in = 0u;
-    if constexpr (VEC) {
-      in = (i >= 0 && i < S) ? 15u : 0u;  // S % 4 == 0 and i % 4 == 0: all four or none
-    } else {
-#pragma unroll
-      for (int s = 0; s < 4; ++s) in |= (i + s >= 0 && i + s < S) ? (1u << s) : 0u;
-    }
-    // A quad with no sample inside the record loads (and then masks) the record's first
-    // samples instead: windows reach past either end of the record for deep pixels at the edge
-    // of the aperture.  Window starts are multiples of 4, so a quad that starts before the
-    // record lies wholly before it; a quad that reaches past the end starts inside it (i < S),
-    // and its samples beyond the end are clamped in issue_stage.  Every load therefore stays
-    // inside element e's record.  (VEC: S % 4 == 0, all four inside or all outside.)
-    const int ic = in ? i : 0;
+    // A quad with no sample inside the record loads the record's first samples instead:
+    // windows reach past either end of the record for deep pixels at the edge of the aperture.
+    // Window starts are multiples of 4, so a quad that starts before the record lies wholly
+    // before it; a quad that reaches past the end starts inside it (i < S), and its samples
+    // beyond the end are clamped in issue_stage (VEC: S % 4 == 0, the quad is wholly inside).
+    // Every load therefore stays inside element e's record.
+    const int ic = (i >= 0 && i < S) ? i : 0;
     d.voff[it] = uint32_t(e0S + sl.kS[it] + ic) * uint32_t(sizeof(int16_t));
-    d.dst[it] = sl.dst[it] | int(in << 26);
+    d.dst[it] = sl.dst[it];
   }
   return d;
 }
@@ -288,24 +326,20 @@ __device__ inline void store_stage(const Prefetch<VEC, FS, IPT>& pf, const Items
   for (int it = 0; it < IPT; ++it) {
     const int dst = it_.dst[it];
     if (dst < 0) continue;
-    const uint32_t in = uint32_t(dst) >> 26;
-    const uint32_t m0 = (in & 1u) ? 0xffffu : 0u, m1 = (in & 2u) ? 0xffff0000u : 0u;
-    const uint32_t m2 = (in & 4u) ? 0xffffu : 0u, m3 = (in & 8u) ? 0xffff0000u : 0u;
     if constexpr (FS == 1) {
-      // int16 window: the four samples as loaded, those outside the record cleared
-      *reinterpret_cast<uint2*>(win + (dst & kDstMask)) =
-          make_uint2(pf.d[it][0].x & (m0 | m1), pf.d[it][0].y & (m2 | m3));
+      // int16 window: the four samples as loaded
+      *reinterpret_cast<uint2*>(win + dst) = pf.d[it][0];
     } else {
       V x[4];
 #pragma unroll
       for (int f = 0; f < FS; ++f) {
-        const uint32_t dx = pf.d[it][f].x & (m0 | m1), dy = pf.d[it][f].y & (m2 | m3);
+        const uint32_t dx = pf.d[it][f].x, dy = pf.d[it][f].y;
         FVec<FS>::set(x[0], f, lo16(dx));
         FVec<FS>::set(x[1], f, hi16(dx));
         FVec<FS>::set(x[2], f, lo16(dy));
         FVec<FS>::set(x[3], f, hi16(dy));
       }
-      V* w = win + (dst & kDstMask);
+      V* w = win + dst;
       if (pshift) {
         w[0] = x[0];
         w[1] = x[2];
@@ -383,7 +417,7 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
   }
   for (int e = tid; e < a.n_el; e += kDasThreads) {
     t.wnd[e] = make_int2(INT_MAX, INT_MIN);
-    t.exy[e] = make_float2(a.el_pos[3 * e], a.el_pos[3 * e + 1]);
+    if constexpr (!one_line_tile<G, FS, SETS>()) t.exy[e] = make_float2(a.el_pos[3 * e], a.el_pos[3 * e + 1]);
   }
   for (int e = tid; e < (a.n_el + 3) / 4; e += kDasThreads) t.flg[e] = 0;
   __syncthreads();
@@ -394,7 +428,7 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
       const LineGeom& Lg = t.lines[gg];
       const ElemGeom E = elem_geom(a, Lg, e);
       const float2 E2 = make_float2(E.A, E.B);
-      t.geo[gg * a.n_el + e] = E2;
+      if constexpr (!one_line_tile<G, FS, SETS>()) t.geo[gg * a.n_el + e] = E2;
       if (l0 + gg % gl >= a.n_lines || Lg.tx < 0) continue;
       if (!in_aperture(SETS ? Lg.F2 : a.F2, a.array_dims, E, r_last)) continue;
       const int shift = 8 * (e & 3);
@@ -465,6 +499,7 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
   // per chunk the parities follow the stage index; with one stage per chunk they follow the
   // chunk ordinal, and the chunk loop is unrolled by two so that they stay compile-time.
   static_assert(NS == 1 || NS % 2 == 0, "stages per chunk must be 1 or even");
+  static_assert(!one_line_tile<G, FS, SETS>() || NS == 1, "one-line tiles stage one frame per chunk");
   Prefetch<VEC, FS, IPT> pf[2];
   const bool stage_any = t_grp >= 0;
   const ItemSlots<IPT> slots = item_slots<IPT, FS>(ta, S);
@@ -478,67 +513,197 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
   };
   // taps of this lane's pixel for chunk c, shared by every frame; a tap that contributes
   // nothing, or whose samples are not staged, reads the zero vector
-  auto make_taps = [&](int c, float& den) {
+  constexpr bool UNI = one_line_tile<G, FS, SETS>();
+  // one-line tiles: tabulate the constants of chunk c's elements into table `ct`, and in its
+  // header the chunk's lateral y offsets when there are at most two of them (a chunk of a matrix
+  // array spans at most two rows).  Lanes 0 .. EC-1 (all in the first wave) each take one element,
+  // whose position `ep` they loaded a chunk earlier (load_ep); the expressions are those of the
+  // general path, so the decisions are the same.
+  auto load_ep = [&](int c) {
+    float3 ep = make_float3(0.0f, 0.0f, 0.0f);
+    const int e = c * ta.ec + tid;
+    if (tid < SH::EC && c >= 0 && c < n_chunks && tid < ta.ec && e < a.n_el)
+      ep = make_float3(a.el_pos[3 * e], a.el_pos[3 * e + 1], a.el_pos[3 * e + 2]);
+    return ep;
+  };
+  auto fill_ctab = [&](int c, ChunkTap* ct, float3 ep) {
+    if (tid >= SH::EC) return;
+    const int k = tid, e = c * ta.ec + k;
+    const bool valid = c >= 0 && c < n_chunks;
+    const bool here = valid && k < ta.ec && e < a.n_el;
+    ChunkTap x;
+    x.A = x.B = x.dx = x.dy = 0.0f;
+    x.thr = __builtin_inff();  // never inside the aperture
+    x.lo = S;
+    x.rng = 0;
+    x.cb = ZERO * int(sizeof(W));
+    if (here) {
+      const ElemGeom E = elem_geom(ep.x, ep.y, ep.z, L);
+      x.A = E.A;
+      x.B = E.B;
+      x.dx = E.dx;
+      x.dy = E.dy;
+      x.thr = a.F2 * (a.array_dims == 2 ? fmaxf(fabsf(E.dx), fabsf(E.dy)) : fabsf(E.dx));
+      // taps read from the window: inside the record, inside the staged samples [ws, hi] and
+      // with both neighbours inside the buffer's span
+      const int2 wd = t.wnd[e];
+      const int ws = wd.x & ~3;
+      const int lo = max(ws, 0);
+      const int hi = min(min(wd.y - 1, ws + ta.span - 2), S - 2);
+      if (on_grp && (wd.x & 2) && hi >= lo) {
+        x.lo = lo;
+        x.rng = hi - lo;
+        x.cb = (k * ta.span + lo - ws) * int(sizeof(W));
+      }
+    }
+    ct[k] = x;
+    // the header, from the lanes' y offsets (lane 0 holds an element whenever the chunk is valid)
+    const float dyA = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x.dy), 0));
+    const uint64_t other = __builtin_amdgcn_ballot_w64(here && x.dy != dyA);
+    float dyB = dyA;
+    int two = 1;
+    if (other != 0) {
+      dyB = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x.dy), __builtin_ctzll(other)));
+      two = __builtin_amdgcn_ballot_w64(here && x.dy != dyA && x.dy != dyB) == 0;
+    }
+    if (k == 0) {
+      ChunkHdr h;
+      h.dyA = dyA;
+      h.dyB = dyB;
+      h.two = two;
+      h.pad = 0;
+      *reinterpret_cast<ChunkHdr*>(ct + SH::EC) = h;
+    }
+  };
+  // taps of a one-line tile from the chunk's table.  MODE (chosen per chunk, wave-uniform): 0 rect
+  // window, 1 Hann over x, 2 separable Hann whose chunk spans at most two y offsets (the y factors
+  // computed once per chunk), 3 separable Hann in general (the y factor kept while the offset
+  // repeats).
+  auto uni_taps = [&](auto mode_, const ChunkTap* ct, float& den) {
+    constexpr int MODE = decltype(mode_)::value;
     Taps T;
     T.slow = 0u;
-    // the chunk is the same for every lane: make that visible, so element data comes
-    // through scalar loads
-    const int e0 = __builtin_amdgcn_readfirstlane(c * ta.ec);
+    const ChunkHdr hd = *reinterpret_cast<const ChunkHdr*>(ct + SH::EC);
+    float hyA = 1.0f, hyB = 1.0f;
+    if constexpr (MODE == 2) {
+      hyA = hann(hd.dyA, inv_w);
+      hyB = hann(hd.dyB, inv_w);
+    }
+    bool slow = false;  // some tap of this lane is inside the record but not in the window
 #pragma unroll
     for (int k = 0; k < SH::EC; ++k) {
       T.off0[k] = T.off1[k] = ZERO * int(sizeof(W));
       T.w0[k] = T.w1[k] = 0.0f;
       if (k >= ta.ec) continue;
-      const int e = min(e0 + k, a.n_el - 1);
-      const float2 E2 = geo[e];
-      const float2 xy = t.exy[e];
-      const ElemGeom E{E2.x, E2.y, xy.x - L.olx, xy.y - L.oly};
-      const bool act = lane_ok && e0 + k < a.n_el && in_aperture(ap_F2, a.array_dims, E, r);
-      if (!__any(act)) continue;  // no lane of the wave needs this element
-      float w = 0.0f;
-      if (act) {
-        if (ap_window == USBF_WINDOW_RECT) {
-          w = 1.0f;
-        } else if (a.array_dims == 2) {
-          // separable window: the y factor is kept while consecutive elements share their row
-          // (a wave-uniform branch: skipped unless some lane meets a new row)
-          if (__any(E.dy != hy_dy)) {
-            hy = hann(E.dy, inv_w);
-            hy_dy = E.dy;
+      const ChunkTap& x = ct[k];
+      const float dy = x.dy;
+      // lanes outside the aperture keep the zero weights; the block is skipped when the whole
+      // wave is outside
+      if ((x.thr <= r) & lane_ok) {
+        float w = 1.0f;
+        if constexpr (MODE >= 1) w = hann(x.dx, inv_w);
+        if constexpr (MODE == 2) w *= dy == hd.dyA ? hyA : hyB;
+        if constexpr (MODE == 3) {
+          if (__any(dy != hy_dy)) {
+            hy = hann(dy, inv_w);
+            hy_dy = dy;
           }
-          w = hann(E.dx, inv_w) * hy;
-        } else {
-          w = hann(E.dx, inv_w);
+          w *= hy;
         }
+        den += w;
+        const Tap tp = fast_tap(a, b, dtx, x.A, x.B, r, r2, rr);
+        const float wp = w * tp.phi;
+        T.w1[k] = wp;
+        T.w0[k] = w - wp;
+        // a tap not summed from the window reads the zero vector (its weights need no masking)
+        const uint32_t d = uint32_t(tp.i0) - uint32_t(x.lo);
+        const bool fast = d <= uint32_t(x.rng);
+        T.off0[k] = fast ? x.cb + int(d) * int(sizeof(W)) : ZERO * int(sizeof(W));
+        slow |= !fast & (uint32_t(tp.i0) <= uint32_t(S - 2));
       }
-      den += w;
-      const Tap tp = fast_tap(a, b, dtx, E.A, E.B, r, r2, rr);
-      const bool ok = act && tp.i0 >= 0 && tp.i0 <= S - 2;
-      const float wp = w * tp.phi;
-      T.w1[k] = ok ? wp : 0.0f;
-      T.w0[k] = ok ? w - wp : 0.0f;
-      const int2 wd = t.wnd[e];
-      const int rel = tp.i0 - (wd.x & ~3);
-      const bool in_win = on_grp && (wd.x & 2) && rel >= 0 && tp.i0 + 1 <= wd.y && rel + 1 < ta.span;
-      const int wbase = k * ta.span;
-      const bool split = FS > 1 && ta.pshift;
-      const int p0 = split ? ((rel & 1) * half + (rel >> 1)) : rel;
-      const int p1 = split ? (((rel + 1) & 1) * half + ((rel + 1) >> 1)) : rel + 1;
-      // byte offsets within a buffer
-      T.off0[k] = ((ok && in_win) ? wbase + p0 : ZERO) * int(sizeof(W));
-      T.off1[k] = ((ok && in_win) ? wbase + p1 : ZERO) * int(sizeof(W));
-      T.slow |= (ok && !in_win) ? (1u << k) : 0u;
     }
+    // slow_taps_uni re-derives, lane by lane, which of the chunk's taps those are
+    T.slow = __any(slow) ? ~0u : 0u;
     return T;
   };
-  // taps outside the staged windows: read global memory
-  auto slow_taps = [&](const Taps& T, int c, int fb, float* acc) {
+  auto make_taps = [&](int c, float& den, int P) {
+    if constexpr (UNI) {
+      const ChunkTap* ct = t.ctab + P * (SH::EC + 1);
+      if (ap_window == USBF_WINDOW_RECT) return uni_taps(std::integral_constant<int, 0>{}, ct, den);
+      if (a.array_dims != 2) return uni_taps(std::integral_constant<int, 1>{}, ct, den);
+      if (reinterpret_cast<const ChunkHdr*>(ct + SH::EC)->two)
+        return uni_taps(std::integral_constant<int, 2>{}, ct, den);
+      return uni_taps(std::integral_constant<int, 3>{}, ct, den);
+    } else {
+      Taps T;
+      T.slow = 0u;
+      // the chunk is the same for every lane: make that visible, so element data comes
+      // through scalar loads
+      const int e0 = __builtin_amdgcn_readfirstlane(c * ta.ec);
+#pragma unroll
+      for (int k = 0; k < SH::EC; ++k) {
+        T.off0[k] = T.off1[k] = ZERO * int(sizeof(W));
+        T.w0[k] = T.w1[k] = 0.0f;
+        if (k >= ta.ec) continue;
+        const int e = min(e0 + k, a.n_el - 1);
+        const float2 E2 = geo[e];
+        const float2 xy = t.exy[e];
+        const ElemGeom E{E2.x, E2.y, xy.x - L.olx, xy.y - L.oly};
+        const bool act = lane_ok && e0 + k < a.n_el && in_aperture(ap_F2, a.array_dims, E, r);
+        if (!__any(act)) continue;  // no lane of the wave needs this element
+        float w = 0.0f;
+        if (act) {
+          if (ap_window == USBF_WINDOW_RECT) {
+            w = 1.0f;
+          } else if (a.array_dims == 2) {
+            // separable window: the y factor is kept while consecutive elements share their row
+            // (a wave-uniform branch: skipped unless some lane meets a new row)
+            if (__any(E.dy != hy_dy)) {
+              hy = hann(E.dy, inv_w);
+              hy_dy = E.dy;
+            }
+            w = hann(E.dx, inv_w) * hy;
+          } else {
+            w = hann(E.dx, inv_w);
+          }
+        }
+        den += w;
+        const Tap tp = fast_tap(a, b, dtx, E.A, E.B, r, r2, rr);
+        const bool ok = act && tp.i0 >= 0 && tp.i0 <= S - 2;
+        const float wp = w * tp.phi;
+        T.w1[k] = ok ? wp : 0.0f;
+        T.w0[k] = ok ? w - wp : 0.0f;
+        const int2 wd = t.wnd[e];
+        const int rel = tp.i0 - (wd.x & ~3);
+        const bool in_win = on_grp && (wd.x & 2) && rel >= 0 && tp.i0 + 1 <= wd.y && rel + 1 < ta.span;
+        const int wbase = k * ta.span;
+        const bool split = FS > 1 && ta.pshift;
+        const int p0 = split ? ((rel & 1) * half + (rel >> 1)) : rel;
+        const int p1 = split ? (((rel + 1) & 1) * half + ((rel + 1) >> 1)) : rel + 1;
+        // byte offsets within a buffer
+        T.off0[k] = ((ok && in_win) ? wbase + p0 : ZERO) * int(sizeof(W));
+        T.off1[k] = ((ok && in_win) ? wbase + p1 : ZERO) * int(sizeof(W));
+        T.slow |= (ok && !in_win) ? (1u << k) : 0u;
+      }
+      return T;
+    }
+  };
+  // one-line tiles: T.slow is set when some lane has a tap inside the record but outside the staged
+  // window; each lane re-derives which of its taps those are (from the whole-tile tables)
+  auto slow_taps_uni = [&](const Taps& T, int c, int fb, float* acc) {
     const int e0 = c * ta.ec;
     for (int k = 0; k < ta.ec; ++k) {
       if (!(T.slow & (1u << k))) continue;
-      const float2 E2 = geo[e0 + k];
-      const Tap tp = fast_tap(a, b, dtx, E2.x, E2.y, r, r2, rr);
-      const int16_t* p = own_block + size_t(e0 + k) * S + tp.i0;
+      const int e = e0 + k;
+      const ElemGeom E = elem_geom(a, L, e);
+      const bool act = lane_ok && in_aperture(a.F2, a.array_dims, E, r);
+      const Tap tp = fast_tap(a, b, dtx, E.A, E.B, r, r2, rr);
+      const int2 wd = t.wnd[e];
+      const int ws = wd.x & ~3;
+      const bool in_rec = tp.i0 >= 0 && tp.i0 <= S - 2;
+      const bool in_win = on_grp && (wd.x & 2) && tp.i0 >= ws && tp.i0 + 1 <= wd.y && tp.i0 - ws + 1 < ta.span;
+      if (!(act && in_rec && !in_win)) continue;
+      const int16_t* p = own_block + size_t(e) * S + tp.i0;
       float sw0 = 0.0f, sw1 = 0.0f;
 #pragma unroll
       for (int kk = 0; kk < SH::EC; ++kk)
@@ -550,6 +715,32 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
       for (int f = 0; f < FB; ++f) {
         const int16_t* q = p + size_t(fb + f) * frame_stride;
         acc[f] = __builtin_fmaf(sw0, float(q[0]), __builtin_fmaf(sw1, float(q[1]), acc[f]));
+      }
+    }
+  };
+  // taps outside the staged windows: read global memory
+  auto slow_taps = [&](const Taps& T, int c, int fb, float* acc) {
+    if constexpr (UNI) {
+      slow_taps_uni(T, c, fb, acc);
+    } else {
+      const int e0 = c * ta.ec;
+      for (int k = 0; k < ta.ec; ++k) {
+        if (!(T.slow & (1u << k))) continue;
+        const float2 E2 = geo[e0 + k];
+        const Tap tp = fast_tap(a, b, dtx, E2.x, E2.y, r, r2, rr);
+        const int16_t* p = own_block + size_t(e0 + k) * S + tp.i0;
+        float sw0 = 0.0f, sw1 = 0.0f;
+#pragma unroll
+        for (int kk = 0; kk < SH::EC; ++kk)
+          if (kk == k) {
+            sw0 = T.w0[kk];
+            sw1 = T.w1[kk];
+          }
+#pragma unroll
+        for (int f = 0; f < FB; ++f) {
+          const int16_t* q = p + size_t(fb + f) * frame_stride;
+          acc[f] = __builtin_fmaf(sw0, float(q[0]), __builtin_fmaf(sw1, float(q[1]), acc[f]));
+        }
       }
     }
   };
@@ -594,6 +785,11 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
       issue_stage<VEC, FS, IPT>(pf[0], items, rsrc, 0u, fbytes, S);
       store_stage<VEC, G, FS, IPT>(pf[0], items, t.win, ta.span, ta.pshift);
       issue_stage<VEC, FS, IPT>(pf[1], items_n, rsrc, 0u, fbytes, S);
+      float3 ep_next = make_float3(0.0f, 0.0f, 0.0f);  // positions for the next table (one-line tiles)
+      if constexpr (UNI) {
+        fill_ctab(c, t.ctab, load_ep(c));
+        ep_next = load_ep(cn);
+      }
       __syncthreads();
       // chunk c sits in LDS buffer P, chunk cn is in flight into register set P ^ 1
       auto body = [&](auto P_) {
@@ -602,7 +798,7 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
         const Items<IPT> items_nn =
             chunk_items<VEC, G, FS, IPT>(t, ta, a, slots, cnn < n_chunks && stage_any ? cnn : -1);
         if (cnn < n_chunks && stage_any) issue_stage<VEC, FS, IPT>(pf[P], items_nn, rsrc, 0u, fbytes, S);
-        const Taps T = make_taps(c, den);
+        const Taps T = make_taps(c, den, P);
         // keep the scheduler from interleaving the tap set-up with the sums (it would hoist
         // LDS reads across it and run out of registers)
         __builtin_amdgcn_sched_barrier(0);
@@ -610,6 +806,10 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
         __builtin_amdgcn_sched_barrier(0);
         if (cn < n_chunks && stage_any)
           store_stage<VEC, G, FS, IPT>(pf[P ^ 1], items_n, t.win + (P ^ 1) * SH::BSTRIDE, ta.span, ta.pshift);
+        if constexpr (UNI) {
+          fill_ctab(cn, t.ctab + (P ^ 1) * (SH::EC + 1), ep_next);
+          ep_next = load_ep(cnn);  // consumed at the end of the next step
+        }
         __syncthreads();
         if (T.slow) slow_taps(T, c, fb, acc);
         c = cn;
@@ -630,7 +830,7 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
         const int cn = next_chunk(c);
         const Items<IPT> next_items =
             chunk_items<VEC, G, FS, IPT>(t, ta, a, slots, cn < n_chunks && stage_any ? cn : -1);
-        const Taps T = make_taps(c, den);
+        const Taps T = make_taps(c, den, 0);
         __builtin_amdgcn_sched_barrier(0);
         auto step = [&](auto s_) {
           constexpr int s = decltype(s_)::value;
@@ -671,8 +871,18 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
 // the aperture of lines near the ends of the array is cut by the array's edge, so contiguous
 // blocks of groups would leave the XCDs holding the edges idle at the end while the others
 // still work on the centre.
+#ifndef USBF_DAS_ONE_LINE_WAVES
+#define USBF_DAS_ONE_LINE_WAVES 1
+#endif
+// waves per SIMD the register allocation must leave room for (1: no constraint)
+template <int G, int FS, bool SETS>
+constexpr int das_min_waves() {
+  return one_line_tile<G, FS, SETS>() ? USBF_DAS_ONE_LINE_WAVES : 1;
+}
+
 template <bool VEC, int G, int FB, int FS, bool SETS>
-__global__ __launch_bounds__(kDasThreads) void das_tile_kernel(const int16_t* __restrict__ rf, int frame0,
+__global__ __launch_bounds__(kDasThreads) __attribute__((amdgpu_waves_per_eu(das_min_waves<G, FS, SETS>())))
+void das_tile_kernel(const int16_t* __restrict__ rf, int frame0,
                                                                int n_blocks, DasArgs a, TileArgs ta,
                                                                float* __restrict__ out) {
   extern __shared__ __align__(16) unsigned char lds_raw[];

@@ -110,15 +110,19 @@ struct ElemGeom {
   float dx, dy; // lateral offsets from the line origin
 };
 
-__device__ inline ElemGeom elem_geom(const DasArgs& a, const LineGeom& L, int e) {
-  const float* ep = a.el_pos + 3 * e;
-  float x = ep[0] - L.olx, y = ep[1] - L.oly, z = ep[2] - L.olz;
+__device__ inline ElemGeom elem_geom(float ex, float ey, float ez, const LineGeom& L) {
+  float x = ex - L.olx, y = ey - L.oly, z = ez - L.olz;
   ElemGeom E;
   E.A = dot3(x, y, z, x, y, z);
   E.B = dot3(x, y, z, L.ulx, L.uly, L.ulz);
   E.dx = x;
   E.dy = y;
   return E;
+}
+
+__device__ inline ElemGeom elem_geom(const DasArgs& a, const LineGeom& L, int e) {
+  const float* ep = a.el_pos + 3 * e;
+  return elem_geom(ep[0], ep[1], ep[2], L);
 }
 
 // |e - p| - r for depth r; r2 = r + r and rr = r * r precomputed per pixel.
