@@ -346,7 +346,7 @@ int usbf_mv_weights_averaged(const float* x, int32_t n_pix, int32_t n_avg, int32
  *   za = IDFT( H . DFT(rf) ),  H as in usbf_envelope (circular over the trace, no padding),
  * written as binary32 (re, im) pairs.
  *   rf  int16 [n_rows][n] (e.g. [n_frames][n_tx][n_el][n_samples] with n_rows = n_frames n_tx n_el)
- *   za  float [n_rows][n][2]
+ *   za  float [n_rows][n][2], 8-byte aligned (USBF_EINVAL otherwise)
  * 8 <= n <= 4096 and every prime factor of n at most 31.
  */
 int usbf_analytic_channels(const int16_t* rf, int64_t n_rows, int32_t n, float* za, hipStream_t stream);

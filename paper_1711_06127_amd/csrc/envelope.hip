@@ -23,7 +23,7 @@ struct FftPlan {
   int radix[kMaxStages];
 };
 
-struct c32 {
+struct alignas(8) c32 {
   float x, y;
 };
 
@@ -32,6 +32,15 @@ struct c32 {
 __host__ __device__ constexpr int pad(int i) { return i + (i >> 4); }
 __host__ __device__ constexpr int padded_len(int n) { return pad(n) + 1; }
 
+// Power-of-two transforms permute LDS indices instead of padding them: bits 0-3 of an index are
+// XORed with bits 3-6 and bits 5-8.  Bit 3 changes only by bits 6 and 8, so the map is a
+// bijection on every aligned block of 16 elements.  On gfx950 8-byte LDS reads are served 32
+// lanes at a time from 64 banks of 4 bytes and 8-byte writes 16 lanes at a time from 32 banks;
+// with this map every stage's reads, writes and twiddle reads take the minimum number of
+// passes (one element of padding per 16 leaves them 2-way).
+__host__ __device__ constexpr int swz(int i) { return i ^ (((i >> 3) ^ (i >> 5)) & 15); }
+__host__ __device__ constexpr int swz_len(int n) { return (n + 15) & ~15; }
+
 __device__ inline c32 cadd(c32 a, c32 b) { return {a.x + b.x, a.y + b.y}; }
 __device__ inline c32 csub(c32 a, c32 b) { return {a.x - b.x, a.y - b.y}; }
 __device__ inline c32 cmul(c32 a, c32 b) {
@@ -39,6 +48,9 @@ __device__ inline c32 cmul(c32 a, c32 b) {
 }
 __device__ inline c32 cscale(c32 a, float s) { return {a.x * s, a.y * s}; }
 __device__ inline c32 mul_mi(c32 a) { return {a.y, -a.x}; }  // -i * a
+// |a|: the hardware square root (within 1 ulp) -- magnitudes are values, compared to 1e-4 of a
+// row's maximum, and the correctly rounded sequence costs some twenty instructions more
+__device__ inline float cabs(float x, float y) { return __builtin_amdgcn_sqrtf(__builtin_fmaf(x, x, y * y)); }
 
 // In-register forward DFTs of size 2, 3, 4, 5 (kernel e^{-2 pi i m q / R}).
 __device__ inline void dft2(c32* v) {
@@ -208,7 +220,7 @@ __device__ inline void stage_ls(const c32* __restrict__ tw, Load load, Store sto
     const int k = j % NS;
     if constexpr (NS > 1) {
       // twiddles W^(r k TWS) as powers of W^(k TWS): one table read per butterfly
-      const c32 w1 = tw[pad(k * TWS)];
+      const c32 w1 = tw[swz(k * TWS)];
       c32 w = w1;
       v[1] = cmul(v[1], w);
 #pragma unroll
@@ -231,11 +243,11 @@ __device__ inline void stage_ls(const c32* __restrict__ tw, Load load, Store sto
 template <int N, int NS, typename Fin>
 __device__ inline void stages_from(c32* a, c32* b, const c32* tw, Fin fin) {
   constexpr int R = radix_at<N, NS>();
-  auto from_a = [&](int j, int r, int M) { return a[pad(j + r * M)]; };
+  auto from_a = [&](int j, int r, int M) { return a[swz(j + r * M)]; };
   if constexpr (NS * R == N) {
     stage_ls<N, NS>(tw, from_a, fin);
   } else {
-    stage_ls<N, NS>(tw, from_a, [&](int i, c32 v) { b[pad(i)] = v; });
+    stage_ls<N, NS>(tw, from_a, [&](int i, c32 v) { b[swz(i)] = v; });
     __syncthreads();
     stages_from<N, NS * R>(b, a, tw, fin);
   }
@@ -262,7 +274,7 @@ __host__ __device__ constexpr int pow2_twiddles() {
 }
 template <int N>
 __host__ __device__ constexpr size_t pow2_lds_bytes() {
-  return (size_t(2) * padded_len(N) + padded_len(pow2_twiddles<N>())) * sizeof(c32);
+  return (size_t(2) * swz_len(N) + swz_len(pow2_twiddles<N>())) * sizeof(c32);
 }
 
 // in == env is allowed (the pipeline detects in place): every row is read whole before any
@@ -273,7 +285,7 @@ __global__ __launch_bounds__(kEnvThreads) void envelope_pow2_kernel(const float*
                                                                     float* __restrict__ row_max) {
   static_assert(N >= 64 && (N & (N - 1)) == 0 && N <= kMaxEnvelopeLength, "power-of-two length");
   extern __shared__ c32 lds[];
-  constexpr int np = padded_len(N);
+  constexpr int np = swz_len(N);
   constexpr int M1 = N / 8;  // butterflies of the first (radix 8) stage
   c32* buf0 = lds;
   c32* buf1 = lds + np;
@@ -282,7 +294,7 @@ __global__ __launch_bounds__(kEnvThreads) void envelope_pow2_kernel(const float*
   for (int k = tid; k < pow2_twiddles<N>(); k += kEnvThreads) {
     float s, c;
     sincospif(2.0f * float(k) / float(N), &s, &c);
-    tw[pad(k)] = {c, -s};
+    tw[swz(k)] = {c, -s};
   }
   __shared__ float red[kEnvThreads / 64];
   // prefetched row, laid out as the first stage reads it: lane j holds x[j + r N/8]
@@ -298,26 +310,34 @@ __global__ __launch_bounds__(kEnvThreads) void envelope_pow2_kernel(const float*
   __syncthreads();  // twiddles
   for (int64_t row = blockIdx.x; row < n_rows; row += gridDim.x) {
     // forward transform: first stage from registers into buf0
-    stage_ls<N, 1>(tw, [&](int, int r, int) { return c32{pre[r], 0.0f}; }, [&](int i, c32 v) { buf0[pad(i)] = v; });
+    stage_ls<N, 1>(tw, [&](int, int r, int) { return c32{pre[r], 0.0f}; }, [&](int i, c32 v) { buf0[swz(i)] = v; });
     if (row + gridDim.x < n_rows) load_row(row + gridDim.x);
     __syncthreads();
     // remaining stages; the last writes H X, conjugated (inverse by forward transform), into
     // the buffer it does not read
     constexpr int src1 = last_src<N, 8>(0);
     c32* spec = src1 == 0 ? buf1 : buf0;
+    // (the bins above N/2 are zero: neither written nor read)
     stages_from<N, 8>(buf0, buf1, tw, [&](int k, c32 v) {
-      const float hk = (k == 0 || k == N / 2) ? 1.0f : (k < N / 2 ? 2.0f : 0.0f);
-      spec[pad(k)] = c32{v.x * hk, -v.y * hk};
+      const float hk = (k == 0 || k == N / 2) ? 1.0f : 2.0f;
+      if (k <= N / 2) spec[swz(k)] = c32{v.x * hk, -v.y * hk};
     });
     __syncthreads();
     c32* other = spec == buf0 ? buf1 : buf0;
-    stage_ls<N, 1>(tw, [&](int j, int r, int M) { return spec[pad(j + r * M)]; },
-                   [&](int i, c32 v) { other[pad(i)] = v; });
+    // inverse, first (radix 8) stage: input j + r N/8 is bin N/2 + j for r = 4 (nonzero only for
+    // j = 0) and above N/2 for r > 4
+    stage_ls<N, 1>(tw,
+                   [&](int j, int r, int M) {
+                     if (r > 4) return c32{0.0f, 0.0f};
+                     if (r == 4) return j == 0 ? spec[swz(N / 2)] : c32{0.0f, 0.0f};
+                     return spec[swz(j + r * M)];
+                   },
+                   [&](int i, c32 v) { other[swz(i)] = v; });
     __syncthreads();
     float mx = 0.0f;
     float* e = env + row * N;
     stages_from<N, 8>(other, spec, tw, [&](int k, c32 v) {
-      const float m = sqrtf(__builtin_fmaf(v.x, v.x, v.y * v.y)) * (1.0f / float(N));
+      const float m = cabs(v.x, v.y) * (1.0f / float(N));
       e[k] = m;
       mx = fmaxf(mx, m);
     });
@@ -445,7 +465,7 @@ __global__ __launch_bounds__(kEnvThreads) void envelope_kernel(const float* in, 
     float* e = env + row * n;
     for (int k = threadIdx.x; k < n; k += kEnvThreads) {
       c32 v = Y[pad(k)];
-      float m = sqrtf(__builtin_fmaf(v.x, v.x, v.y * v.y)) * inv_n;
+      float m = cabs(v.x, v.y) * inv_n;
       e[k] = m;
       mx = fmaxf(mx, m);
     }
@@ -564,6 +584,7 @@ int envelope_enqueue(const float* in, int64_t n_rows, int n, float* env, float* 
 extern "C" int usbf_analytic_channels(const int16_t* rf, int64_t n_rows, int32_t n, float* za, hipStream_t stream) {
   using namespace usbf;
   USBF_REQUIRE(rf && za, USBF_EINVAL, "null rf or za");
+  USBF_REQUIRE((reinterpret_cast<uintptr_t>(za) & 7) == 0, USBF_EINVAL, "za must be 8-byte aligned");
   USBF_REQUIRE(n_rows >= 1, USBF_EINVAL, "n_rows must be >= 1");
   USBF_REQUIRE(n >= 8 && n <= kMaxAnalyticLength, USBF_EUNSUPPORTED, "trace length %d outside 8..%d", n,
                kMaxAnalyticLength);

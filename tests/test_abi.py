@@ -139,6 +139,7 @@ def test_analytic_and_complex_gather_reject(u):
     assert L.usbf_analytic_channels(FAKE, 4, 4, FAKE, None) == -3
     assert L.usbf_analytic_channels(FAKE, 4, 8192, FAKE, None) == -3          # longer than 4096
     assert L.usbf_analytic_channels(FAKE, 4, 37 * 64, FAKE, None) == -3       # prime factor 37
+    assert L.usbf_analytic_channels(FAKE, 4, 1024, FAKE + 4, None) == -1      # za not 8-byte aligned
     g, r = geom(u), rx(u)
     assert L.usbf_delay_gather_complex(None, 1, ctypes.byref(g), ctypes.byref(r), FAKE, 4, FAKE, None) == -1
     assert L.usbf_delay_gather_complex(FAKE, 1, ctypes.byref(g), ctypes.byref(r), FAKE, 0, FAKE, None) == -1
