@@ -103,14 +103,22 @@ struct Shape {
   static constexpr int IPT = (EC * (SPAN / 4) + kDasThreads - 1) / kDasThreads;
 };
 
-// Tiles of one line and one frame (3D volumes, single-line frames): every lane of the workgroup
-// beamforms the same line, so everything about an element except the depth is the same for all
-// lanes.  For each chunk the workgroup tabulates those element constants once, next to the
-// chunk's staging buffer, and the lanes read them with two broadcast LDS reads per element
-// instead of re-deriving them per pixel.
+// Tiles of one line (3D volumes, single-line frames): everything about an element except the
+// depth is the same for all lanes.  For each chunk the workgroup tabulates those constants once
+// per element, next to the chunk's staging buffer, and the lanes read them with two broadcast
+// LDS reads per element instead of re-deriving them per pixel.  (The code handles any tile
+// whose waves each cover one line, G <= 4; for the multi-line multi-frame tiles, whose taps
+// serve up to 32 frames, the extra registers of the table path cost more than it saves.)
 template <int G, int FS, bool SETS = false>
-__host__ __device__ constexpr bool one_line_tile() {
-  return G == 1 && FS == 1 && !SETS;
+__host__ __device__ constexpr bool line_per_wave() {
+  return G == 1 && !SETS;
+}
+// The one-line single-frame tile (3D volumes; many elements, little reuse) keeps no
+// per-element geometry tables in LDS: the lanes that tabulate a chunk load the positions from
+// the geometry arrays a chunk ahead.
+template <int G, int FS>
+__host__ __device__ constexpr bool geo_from_global() {
+  return G == 1 && FS == 1;
 }
 
 struct alignas(16) ChunkTap {
@@ -118,9 +126,9 @@ struct alignas(16) ChunkTap {
   float dx;    // lateral x offset (Hann factor)
   float dy;    // lateral y offset
   float thr;   // F2 times the lateral offset the aperture tests: inside iff thr <= r
-  int cb;      // taps i0 in [lo, lo + rng] are summed from the staged window, whose sample lo
-  int lo;      // sits at byte cb of the buffer (lo = n_samples, rng = 0 and cb = the zero vector
-  int rng;     // when nothing is staged: that tap is outside the record)
+  int base;    // taps i0 in [lo, lo + n) are summed from the staged window (n = 0 when nothing
+  int lo;      // is staged); base is the byte offset of tap lo in the buffer for int16 windows
+  int n;       // (FS = 1), the window's first sample for FS > 1
 };
 
 // after a chunk's table: its elements' lateral y offsets if there are at most two of them
@@ -135,13 +143,17 @@ static_assert(sizeof(ChunkHdr) <= sizeof(ChunkTap), "the header takes one table 
 // G lines, their LineGeom, and per element the tap window [lo, hi] and flags.
 // A staged window holds the samples of one element for FS frames; with pshift = 1 (and FS > 1:
 // single-frame windows are read 4 bytes per lane, where the split does not pay) it is split
-// into even and odd samples (sample i at index (i & 1) * span/2 + i/2): lanes on consecutive
-// depths read taps depth_step = 2 samples apart, so their reads are consecutive in LDS.
+// into even and odd samples, sample i at index (i & 1) * span/2 + half_slot(i / 2): lanes on
+// consecutive depths read taps depth_step = 2 samples apart, so their reads are consecutive in
+// LDS.  half_slot swaps the two vectors of every other pair of quads (index m ^ bit 3 of m):
+// a staging item writes indices 2q and 2q + 1 of each half for its quad q, and on gfx950
+// 16-byte LDS writes are served 8 lanes at a time from 32 banks, so without the swap the 8
+// lanes of a pass would write 4 distinct bank groups twice; reads are unaffected.
 template <int G, int FS>
 struct TileLds {
   typename WinT<FS>::T* win;  // [2][BSTRIDE]: window data, then all-zero vectors
-  ChunkTap* ctab;             // [2][EC + 1], one-line tiles only: element constants of each buffer's
-                              // chunk, then its header (ChunkHdr)
+  ChunkTap* ctab;             // [2][G][EC + 1], line_per_wave tiles only: element constants of each
+                              // buffer's chunk for each line, then the line's header (ChunkHdr)
   float2* geo;                // [G][n_el]: (A, B) of the receive path
   float2* exy;                // [n_el]: element x, y (lateral offsets are taken from the lines)
   LineGeom* lines;            // [G]
@@ -159,32 +171,32 @@ __host__ __device__ constexpr size_t window_bytes() {
   return 2 * size_t(Shape<G, FS>::BSTRIDE) * sizeof(typename WinT<FS>::T);
 }
 
-template <int G, int FS>
+template <int G, int FS, bool SETS>
 __host__ __device__ constexpr size_t ctab_bytes() {
-  return one_line_tile<G, FS>() ? 2 * size_t(Shape<G, FS>::EC + 1) * sizeof(ChunkTap) : 0;
+  return line_per_wave<G, FS, SETS>() ? 2 * size_t(G) * (Shape<G, FS>::EC + 1) * sizeof(ChunkTap) : 0;
 }
 
 // per-(line, element) receive constants and element positions (one-line tiles derive them from
 // the geometry arrays when they tabulate a chunk instead)
 template <int G, int FS>
 __host__ __device__ constexpr size_t geo_entries(int n_el) {
-  return one_line_tile<G, FS>() ? 0 : size_t(G + 1) * n_el;
+  return geo_from_global<G, FS>() ? 0 : size_t(G + 1) * n_el;
 }
 
-template <int G, int FS>
+template <int G, int FS, bool SETS = false>
 __host__ __device__ inline size_t tile_lds_bytes(int n_el) {
-  return window_bytes<G, FS>() + ctab_bytes<G, FS>() + geo_entries<G, FS>(n_el) * sizeof(float2) +
+  return window_bytes<G, FS>() + ctab_bytes<G, FS, SETS>() + geo_entries<G, FS>(n_el) * sizeof(float2) +
          G * sizeof(LineGeom) + size_t(n_el) * sizeof(int2) + size_t((n_el + 3) / 4) * sizeof(int);
 }
 
-template <int G, int FS>
+template <int G, int FS, bool SETS = false>
 __device__ inline TileLds<G, FS> carve(unsigned char* base, int n_el) {
   static_assert(window_bytes<G, FS>() % 16 == 0, "the tap table after the buffers needs 16-byte alignment");
   TileLds<G, FS> t;
   t.win = reinterpret_cast<typename WinT<FS>::T*>(base);
   t.ctab = reinterpret_cast<ChunkTap*>(base + window_bytes<G, FS>());
-  t.geo = reinterpret_cast<float2*>(base + window_bytes<G, FS>() + ctab_bytes<G, FS>());
-  t.exy = t.geo + size_t(G) * n_el;  // (neither table exists in one-line tiles)
+  t.geo = reinterpret_cast<float2*>(base + window_bytes<G, FS>() + ctab_bytes<G, FS, SETS>());
+  t.exy = t.geo + size_t(G) * n_el;  // (neither table exists when geo_from_global)
   t.lines = reinterpret_cast<LineGeom*>(t.geo + geo_entries<G, FS>(n_el));
   t.wnd = reinterpret_cast<int2*>(t.lines + G);
   t.flg = reinterpret_cast<int*>(t.wnd + n_el);
@@ -205,12 +217,16 @@ __device__ inline void set_params(const DasArgs& a, int s, LineGeom& L) {
   L.window = s == 0 ? a.set_window[0] : s == 1 ? a.set_window[1] : s == 2 ? a.set_window[2] : a.set_window[3];
 }
 
+// index within one half of a split window (see TileLds)
+__host__ __device__ constexpr int half_slot(int m) { return m ^ ((m >> 3) & 1); }
+
 __device__ inline float lo16(uint32_t d) { return float(int16_t(d & 0xffffu)); }
 __device__ inline float hi16(uint32_t d) { return float(int16_t(d >> 16)); }
 
 // One staging item: four consecutive samples of one element's window.  `voff` is the byte
 // offset of the first sample within the transmit's block of a frame (clamped into the
-// record); `dst` the window-relative LDS index of the first sample; dst < 0: nothing to stage.
+// record); `dst` the window-relative LDS index of the first sample, bit 30 set when a split
+// window swaps the quad's vectors (half_slot); dst < 0: nothing to stage.
 // Window samples outside the record are staged as whatever the clamped load returns: a tap is
 // summed from the window only when both of its samples lie inside the record, so they are
 // never read.
@@ -229,7 +245,7 @@ struct ItemSlots {
   int k[IPT];      // element of the chunk
   int q4[IPT];     // first sample of the quad within the window
   int kS[IPT];     // k * n_samples: the element's record relative to the chunk's first
-  int dst[IPT];    // window-relative LDS index of the quad's first sample
+  int dst[IPT];    // window-relative LDS index of the quad's first sample (bit 30: vectors swapped)
 };
 
 template <int IPT, int FS>
@@ -243,7 +259,8 @@ __device__ inline ItemSlots<IPT> item_slots(const TileArgs& ta, int S) {
     s.k[it] = k;
     s.q4[it] = 4 * q;
     s.kS[it] = k * S;
-    s.dst[it] = k * ta.span + ((FS > 1 && ta.pshift) ? 2 * q : 4 * q);
+    // split windows: bit 30 says the quad's two vectors per half are swapped (half_slot)
+    s.dst[it] = (FS > 1 && ta.pshift) ? (k * ta.span + 2 * q) | (((q >> 2) & 1) << 30) : k * ta.span + 4 * q;
   }
   return s;
 }
@@ -339,12 +356,15 @@ __device__ inline void store_stage(const Prefetch<VEC, FS, IPT>& pf, const Items
         FVec<FS>::set(x[2], f, lo16(dy));
         FVec<FS>::set(x[3], f, hi16(dy));
       }
-      V* w = win + dst;
+      V* w = win + (dst & 0x3fffffff);
       if (pshift) {
-        w[0] = x[0];
-        w[1] = x[2];
-        w[half] = x[1];
-        w[half + 1] = x[3];
+        // samples 4q and 4q + 2 go to half indices 2q and 2q + 1, swapped when bit 2 of q is
+        // set (half_slot)
+        const int f = dst >> 30;
+        w[f] = x[0];
+        w[1 - f] = x[2];
+        w[half + f] = x[1];
+        w[half + 1 - f] = x[3];
       } else {
         w[0] = x[0];
         w[1] = x[1];
@@ -379,7 +399,7 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
   constexpr int TD = SH::TD;
   constexpr int NS = FB / FS;
   constexpr int IPT = SH::IPT;
-  const TileLds<G, FS> t = carve<G, FS>(lds_raw, a.n_el);
+  const TileLds<G, FS> t = carve<G, FS, SETS>(lds_raw, a.n_el);
 
   const int tid = threadIdx.x;
   // slot g of the tile: line l0 + g % gl with apodization set g / gl (gl = G with one set)
@@ -417,7 +437,7 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
   }
   for (int e = tid; e < a.n_el; e += kDasThreads) {
     t.wnd[e] = make_int2(INT_MAX, INT_MIN);
-    if constexpr (!one_line_tile<G, FS, SETS>()) t.exy[e] = make_float2(a.el_pos[3 * e], a.el_pos[3 * e + 1]);
+    if constexpr (!geo_from_global<G, FS>()) t.exy[e] = make_float2(a.el_pos[3 * e], a.el_pos[3 * e + 1]);
   }
   for (int e = tid; e < (a.n_el + 3) / 4; e += kDasThreads) t.flg[e] = 0;
   __syncthreads();
@@ -428,7 +448,7 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
       const LineGeom& Lg = t.lines[gg];
       const ElemGeom E = elem_geom(a, Lg, e);
       const float2 E2 = make_float2(E.A, E.B);
-      if constexpr (!one_line_tile<G, FS, SETS>()) t.geo[gg * a.n_el + e] = E2;
+      if constexpr (!geo_from_global<G, FS>()) t.geo[gg * a.n_el + e] = E2;
       if (l0 + gg % gl >= a.n_lines || Lg.tx < 0) continue;
       if (!in_aperture(SETS ? Lg.F2 : a.F2, a.array_dims, E, r_last)) continue;
       const int shift = 8 * (e & 3);
@@ -499,7 +519,6 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
   // per chunk the parities follow the stage index; with one stage per chunk they follow the
   // chunk ordinal, and the chunk loop is unrolled by two so that they stay compile-time.
   static_assert(NS == 1 || NS % 2 == 0, "stages per chunk must be 1 or even");
-  static_assert(!one_line_tile<G, FS, SETS>() || NS == 1, "one-line tiles stage one frame per chunk");
   Prefetch<VEC, FS, IPT> pf[2];
   const bool stage_any = t_grp >= 0;
   const ItemSlots<IPT> slots = item_slots<IPT, FS>(ta, S);
@@ -513,12 +532,15 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
   };
   // taps of this lane's pixel for chunk c, shared by every frame; a tap that contributes
   // nothing, or whose samples are not staged, reads the zero vector
-  constexpr bool UNI = one_line_tile<G, FS, SETS>();
-  // one-line tiles: tabulate the constants of chunk c's elements into table `ct`, and in its
-  // header the chunk's lateral y offsets when there are at most two of them (a chunk of a matrix
-  // array spans at most two rows).  Lanes 0 .. EC-1 (all in the first wave) each take one element,
-  // whose position `ep` they loaded a chunk earlier (load_ep); the expressions are those of the
-  // general path, so the decisions are the same.
+  constexpr bool UNI = line_per_wave<G, FS, SETS>();
+  constexpr bool GEO_G = geo_from_global<G, FS>();
+  constexpr int EC1 = SH::EC + 1;  // table entries per (buffer, line): the chunk's, then a header
+  // line_per_wave tiles: tabulate the constants of chunk c's elements for every line of the tile
+  // into table buffer tb, and in each line's header the chunk's lateral y offsets when there are
+  // at most two of them (a chunk of a matrix array spans at most two rows).  Lanes
+  // 0 .. G EC - 1 (all in the first wave) take one (line, element) each; the expressions are
+  // those of the general path below, so the decisions are the same.  With GEO_G the positions
+  // come from `ep`, loaded a chunk earlier (load_ep), otherwise from the LDS tables.
   auto load_ep = [&](int c) {
     float3 ep = make_float3(0.0f, 0.0f, 0.0f);
     const int e = c * ta.ec + tid;
@@ -526,19 +548,28 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
       ep = make_float3(a.el_pos[3 * e], a.el_pos[3 * e + 1], a.el_pos[3 * e + 2]);
     return ep;
   };
-  auto fill_ctab = [&](int c, ChunkTap* ct, float3 ep) {
-    if (tid >= SH::EC) return;
-    const int k = tid, e = c * ta.ec + k;
+  auto fill_ctab = [&](int c, int tb, float3 ep) {
+    if (tid >= G * SH::EC) return;
+    const int gg = tid / SH::EC, k = tid - gg * SH::EC, e = c * ta.ec + k;
+    const LineGeom& Lg = t.lines[gg];
     const bool valid = c >= 0 && c < n_chunks;
     const bool here = valid && k < ta.ec && e < a.n_el;
+    const bool on_g = l0 + gg < a.n_lines && Lg.tx >= 0 && Lg.tx == t_grp;
     ChunkTap x;
     x.A = x.B = x.dx = x.dy = 0.0f;
     x.thr = __builtin_inff();  // never inside the aperture
-    x.lo = S;
-    x.rng = 0;
-    x.cb = ZERO * int(sizeof(W));
+    x.lo = 0;
+    x.n = 0;
+    x.base = 0;
     if (here) {
-      const ElemGeom E = elem_geom(ep.x, ep.y, ep.z, L);
+      ElemGeom E;
+      if constexpr (GEO_G) {
+        E = elem_geom(ep.x, ep.y, ep.z, Lg);
+      } else {
+        const float2 E2 = t.geo[gg * a.n_el + e];
+        const float2 xy = t.exy[e];
+        E = ElemGeom{E2.x, E2.y, xy.x - Lg.olx, xy.y - Lg.oly};
+      }
       x.A = E.A;
       x.B = E.B;
       x.dx = E.dx;
@@ -550,21 +581,25 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
       const int ws = wd.x & ~3;
       const int lo = max(ws, 0);
       const int hi = min(min(wd.y - 1, ws + ta.span - 2), S - 2);
-      if (on_grp && (wd.x & 2) && hi >= lo) {
+      if (on_g && (wd.x & 2) && hi >= lo) {
         x.lo = lo;
-        x.rng = hi - lo;
-        x.cb = (k * ta.span + lo - ws) * int(sizeof(W));
+        x.n = hi - lo + 1;
+        x.base = FS == 1 ? (k * ta.span + lo - ws) * int(sizeof(W)) : ws;
       }
     }
+    ChunkTap* ct = t.ctab + (tb * G + gg) * EC1;
     ct[k] = x;
-    // the header, from the lanes' y offsets (lane 0 holds an element whenever the chunk is valid)
-    const float dyA = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x.dy), 0));
-    const uint64_t other = __builtin_amdgcn_ballot_w64(here && x.dy != dyA);
+    // the line's header, from the y offsets of its lanes (its first lane holds an element
+    // whenever the chunk is valid)
+    const int first = gg * SH::EC;
+    const uint64_t mine = ((uint64_t(1) << SH::EC) - 1) << first;
+    const float dyA = __shfl(x.dy, first);
+    const uint64_t other = __builtin_amdgcn_ballot_w64(here && x.dy != dyA) & mine;
     float dyB = dyA;
     int two = 1;
     if (other != 0) {
-      dyB = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x.dy), __builtin_ctzll(other)));
-      two = __builtin_amdgcn_ballot_w64(here && x.dy != dyA && x.dy != dyB) == 0;
+      dyB = __shfl(x.dy, int(__builtin_ctzll(other)));
+      two = (__builtin_amdgcn_ballot_w64(here && x.dy != dyA && x.dy != dyB) & mine) == 0;
     }
     if (k == 0) {
       ChunkHdr h;
@@ -575,7 +610,7 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
       *reinterpret_cast<ChunkHdr*>(ct + SH::EC) = h;
     }
   };
-  // taps of a one-line tile from the chunk's table.  MODE (chosen per chunk, wave-uniform): 0 rect
+  // taps of a line_per_wave tile from the table of the wave's line.  MODE (chosen per chunk, wave-uniform): 0 rect
   // window, 1 Hann over x, 2 separable Hann whose chunk spans at most two y offsets (the y factors
   // computed once per chunk), 3 separable Hann in general (the y factor kept while the offset
   // repeats).
@@ -617,10 +652,21 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
         T.w0[k] = w - wp;
         // a tap not summed from the window reads the zero vector (its weights need no masking)
         const uint32_t d = uint32_t(tp.i0) - uint32_t(x.lo);
-        const bool fast = d <= uint32_t(x.rng);
-        T.off0[k] = fast ? x.cb + int(d) * int(sizeof(W)) : ZERO * int(sizeof(W));
+        const bool fast = d < uint32_t(x.n);
+        if constexpr (FS == 1) {
+          T.off0[k] = fast ? x.base + int(d) * int(sizeof(W)) : ZERO * int(sizeof(W));
+        } else {
+          const int rel = tp.i0 - x.base, wbase = k * ta.span;
+          const int p0 = ta.pshift ? ((rel & 1) * half + half_slot(rel >> 1)) : rel;
+          const int p1 = ta.pshift ? (((rel + 1) & 1) * half + half_slot((rel + 1) >> 1)) : rel + 1;
+          T.off0[k] = (fast ? wbase + p0 : ZERO) * int(sizeof(W));
+          T.off1[k] = (fast ? wbase + p1 : ZERO) * int(sizeof(W));
+        }
         slow |= !fast & (uint32_t(tp.i0) <= uint32_t(S - 2));
       }
+      // one element at a time: hoisting the table reads of later elements would hold them all
+      // in registers at once
+      if constexpr (FS > 1) __builtin_amdgcn_sched_barrier(0);
     }
     // slow_taps_uni re-derives, lane by lane, which of the chunk's taps those are
     T.slow = __any(slow) ? ~0u : 0u;
@@ -628,7 +674,7 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
   };
   auto make_taps = [&](int c, float& den, int P) {
     if constexpr (UNI) {
-      const ChunkTap* ct = t.ctab + P * (SH::EC + 1);
+      const ChunkTap* ct = t.ctab + (P * G + g) * EC1;
       if (ap_window == USBF_WINDOW_RECT) return uni_taps(std::integral_constant<int, 0>{}, ct, den);
       if (a.array_dims != 2) return uni_taps(std::integral_constant<int, 1>{}, ct, den);
       if (reinterpret_cast<const ChunkHdr*>(ct + SH::EC)->two)
@@ -678,8 +724,8 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
         const bool in_win = on_grp && (wd.x & 2) && rel >= 0 && tp.i0 + 1 <= wd.y && rel + 1 < ta.span;
         const int wbase = k * ta.span;
         const bool split = FS > 1 && ta.pshift;
-        const int p0 = split ? ((rel & 1) * half + (rel >> 1)) : rel;
-        const int p1 = split ? (((rel + 1) & 1) * half + ((rel + 1) >> 1)) : rel + 1;
+        const int p0 = split ? ((rel & 1) * half + half_slot(rel >> 1)) : rel;
+        const int p1 = split ? (((rel + 1) & 1) * half + half_slot((rel + 1) >> 1)) : rel + 1;
         // byte offsets within a buffer
         T.off0[k] = ((ok && in_win) ? wbase + p0 : ZERO) * int(sizeof(W));
         T.off1[k] = ((ok && in_win) ? wbase + p1 : ZERO) * int(sizeof(W));
@@ -785,10 +831,10 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
       issue_stage<VEC, FS, IPT>(pf[0], items, rsrc, 0u, fbytes, S);
       store_stage<VEC, G, FS, IPT>(pf[0], items, t.win, ta.span, ta.pshift);
       issue_stage<VEC, FS, IPT>(pf[1], items_n, rsrc, 0u, fbytes, S);
-      float3 ep_next = make_float3(0.0f, 0.0f, 0.0f);  // positions for the next table (one-line tiles)
+      float3 ep_next = make_float3(0.0f, 0.0f, 0.0f);  // positions for the next table (GEO_G)
       if constexpr (UNI) {
-        fill_ctab(c, t.ctab, load_ep(c));
-        ep_next = load_ep(cn);
+        fill_ctab(c, 0, GEO_G ? load_ep(c) : ep_next);
+        if constexpr (GEO_G) ep_next = load_ep(cn);
       }
       __syncthreads();
       // chunk c sits in LDS buffer P, chunk cn is in flight into register set P ^ 1
@@ -807,8 +853,8 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
         if (cn < n_chunks && stage_any)
           store_stage<VEC, G, FS, IPT>(pf[P ^ 1], items_n, t.win + (P ^ 1) * SH::BSTRIDE, ta.span, ta.pshift);
         if constexpr (UNI) {
-          fill_ctab(cn, t.ctab + (P ^ 1) * (SH::EC + 1), ep_next);
-          ep_next = load_ep(cnn);  // consumed at the end of the next step
+          fill_ctab(cn, P ^ 1, ep_next);
+          if constexpr (GEO_G) ep_next = load_ep(cnn);  // consumed at the end of the next step
         }
         __syncthreads();
         if (T.slow) slow_taps(T, c, fb, acc);
@@ -825,12 +871,14 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
       issue_stage<VEC, FS, IPT>(pf[0], items, rsrc, 0u, fbytes, S);
       store_stage<VEC, G, FS, IPT>(pf[0], items, t.win, ta.span, ta.pshift);
       issue_stage<VEC, FS, IPT>(pf[1], items, rsrc, uint32_t(FS) * fbytes, fbytes, S);
+      int tb = 0;  // table buffer of chunk c (line_per_wave tiles)
+      if constexpr (UNI) fill_ctab(c, 0, make_float3(0.0f, 0.0f, 0.0f));
       __syncthreads();
       while (c < n_chunks) {
         const int cn = next_chunk(c);
         const Items<IPT> next_items =
             chunk_items<VEC, G, FS, IPT>(t, ta, a, slots, cn < n_chunks && stage_any ? cn : -1);
-        const Taps T = make_taps(c, den, 0);
+        const Taps T = make_taps(c, den, tb);
         __builtin_amdgcn_sched_barrier(0);
         auto step = [&](auto s_) {
           constexpr int s = decltype(s_)::value;
@@ -846,9 +894,13 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
           if (has_next)
             store_stage<VEC, G, FS, IPT>(pf[(s + 1) & 1], last ? next_items : items,
                                          t.win + ((s + 1) & 1) * SH::BSTRIDE, ta.span, ta.pshift);
+          // the next chunk's table, into the buffer this chunk's taps did not read (in the last
+          // stage, where they are no longer live)
+          if constexpr (UNI && last) fill_ctab(cn, tb ^ 1, make_float3(0.0f, 0.0f, 0.0f));
           __syncthreads();
         };
         static_for<NS>(step);
+        tb ^= 1;
         if (T.slow) slow_taps(T, c, fb, acc);
         items = next_items;
         c = cn;
@@ -877,7 +929,7 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
 // waves per SIMD the register allocation must leave room for (1: no constraint)
 template <int G, int FS, bool SETS>
 constexpr int das_min_waves() {
-  return one_line_tile<G, FS, SETS>() ? USBF_DAS_ONE_LINE_WAVES : 1;
+  return (line_per_wave<G, FS, SETS>() && geo_from_global<G, FS>()) ? USBF_DAS_ONE_LINE_WAVES : 1;
 }
 
 template <bool VEC, int G, int FB, int FS, bool SETS>
@@ -922,7 +974,7 @@ int launch_das(const int16_t* rf, int frame0, int n_blocks, const DasArgs& a, fl
   const int gl = SETS ? G / a.n_sets : G;  // lines per tile
   const int64_t blocks = int64_t((a.n_lines + gl - 1) / gl) * ta.n_dtiles;
   if (blocks > 0x7fffffff) return fail(USBF_EUNSUPPORTED, "too many tiles");
-  const size_t lds = tile_lds_bytes<G, FS>(a.n_el);
+  const size_t lds = tile_lds_bytes<G, FS, SETS>(a.n_el);
   if (lds > size_t(kMaxTileLds))
     return fail(USBF_EUNSUPPORTED, "%d elements need %zu bytes of LDS per tile", a.n_el, lds);
   const bool vec = (a.n_samples % 4) == 0 && (reinterpret_cast<uintptr_t>(rf) & 7) == 0;
