@@ -157,8 +157,9 @@ struct TileLds {
   float2* geo;                // [G][n_el]: (A, B) of the receive path
   float2* exy;                // [n_el]: element x, y (lateral offsets are taken from the lines)
   LineGeom* lines;            // [G]
-  int2* wnd;                  // [n_el]: (lo | flags, hi); lo a multiple of 4, flags bit 0 needed,
-                              // bit 1 staged
+  int4* wnd;                  // [n_el]: (lo | flags, hi, flo, fn); lo a multiple of 4, flags bit 0
+                              // needed, bit 1 staged; taps i0 in [flo, flo + fn) are summed from
+                              // the staged window (inside the record, the window and its span)
   int* flg;                   // [(n_el + 3) / 4]: the flags, a byte per element, while they are built
 };
 
@@ -186,7 +187,7 @@ __host__ __device__ constexpr size_t geo_entries(int n_el) {
 template <int G, int FS, bool SETS = false>
 __host__ __device__ inline size_t tile_lds_bytes(int n_el) {
   return window_bytes<G, FS>() + ctab_bytes<G, FS, SETS>() + geo_entries<G, FS>(n_el) * sizeof(float2) +
-         G * sizeof(LineGeom) + size_t(n_el) * sizeof(int2) + size_t((n_el + 3) / 4) * sizeof(int);
+         G * sizeof(LineGeom) + size_t(n_el) * sizeof(int4) + size_t((n_el + 3) / 4) * sizeof(int);
 }
 
 template <int G, int FS, bool SETS = false>
@@ -198,7 +199,7 @@ __device__ inline TileLds<G, FS> carve(unsigned char* base, int n_el) {
   t.geo = reinterpret_cast<float2*>(base + window_bytes<G, FS>() + ctab_bytes<G, FS, SETS>());
   t.exy = t.geo + size_t(G) * n_el;  // (neither table exists when geo_from_global)
   t.lines = reinterpret_cast<LineGeom*>(t.geo + geo_entries<G, FS>(n_el));
-  t.wnd = reinterpret_cast<int2*>(t.lines + G);
+  t.wnd = reinterpret_cast<int4*>(t.lines + G);
   t.flg = reinterpret_cast<int*>(t.wnd + n_el);
   return t;
 }
@@ -279,7 +280,7 @@ __device__ inline Items<IPT> chunk_items(const TileLds<G, FS>& t, const TileArgs
     d.voff[it] = 0u;
     d.dst[it] = -1;
     if (k >= ec || c < 0) continue;
-    const int2 wd = t.wnd[e];
+    const int4 wd = t.wnd[e];
     const int i = (wd.x & ~3) + sl.q4[it];
     if (!(wd.x & 2) || i > wd.y) continue;
     // A quad with no sample inside the record loads the record's first samples instead:
@@ -436,7 +437,7 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
       for (int k = ZERO; k < SH::BSTRIDE; ++k) t.win[b * SH::BSTRIDE + k] = z;
   }
   for (int e = tid; e < a.n_el; e += kDasThreads) {
-    t.wnd[e] = make_int2(INT_MAX, INT_MIN);
+    t.wnd[e] = make_int4(INT_MAX, INT_MIN, 0, 0);
     if constexpr (!geo_from_global<G, FS>()) t.exy[e] = make_float2(a.el_pos[3 * e], a.el_pos[3 * e + 1]);
   }
   for (int e = tid; e < (a.n_el + 3) / 4; e += kDasThreads) t.flg[e] = 0;
@@ -462,19 +463,25 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
     }
   }
   __syncthreads();
-  // window start aligned down to 4 samples, flags folded into its two low bits
+  // window start aligned down to 4 samples, flags folded into its two low bits; the taps summed
+  // from the window: inside the record (both samples), at or after its start, with the next
+  // sample staged and inside the buffer's span
   for (int e = tid; e < a.n_el; e += kDasThreads) {
     const int f = (t.flg[e >> 2] >> (8 * (e & 3))) & 3;
-    int lo4 = 0;
+    const int hi = t.wnd[e].y;
+    int lo4 = 0, flo = 0, fn = 0;
     if (f & 2) {
-      const int lo = t.wnd[e].x, hi = t.wnd[e].y;
+      const int lo = t.wnd[e].x;
       lo4 = lo >= 0 ? (lo & ~3) : -((-lo + 3) & ~3);
       if (hi - lo4 + 1 > ta.span) {  // wider than the buffer: keep the deep end
         lo4 = hi + 1 - ta.span;
         lo4 = lo4 >= 0 ? ((lo4 + 3) & ~3) : -((-lo4) & ~3);
       }
+      flo = max(lo4, 0);
+      const int fhi = min(min(hi - 1, lo4 + ta.span - 2), S - 2);
+      fn = fhi >= flo ? fhi - flo + 1 : 0;
     }
-    t.wnd[e].x = lo4 | f;
+    t.wnd[e] = make_int4(lo4 | f, hi, flo, fn);
   }
   __syncthreads();
 
@@ -577,14 +584,12 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
       x.thr = a.F2 * (a.array_dims == 2 ? fmaxf(fabsf(E.dx), fabsf(E.dy)) : fabsf(E.dx));
       // taps read from the window: inside the record, inside the staged samples [ws, hi] and
       // with both neighbours inside the buffer's span
-      const int2 wd = t.wnd[e];
+      const int4 wd = t.wnd[e];
       const int ws = wd.x & ~3;
-      const int lo = max(ws, 0);
-      const int hi = min(min(wd.y - 1, ws + ta.span - 2), S - 2);
-      if (on_g && (wd.x & 2) && hi >= lo) {
-        x.lo = lo;
-        x.n = hi - lo + 1;
-        x.base = FS == 1 ? (k * ta.span + lo - ws) * int(sizeof(W)) : ws;
+      if (on_g) {
+        x.lo = wd.z;
+        x.n = wd.w;
+        x.base = FS == 1 ? (k * ta.span + wd.z - ws) * int(sizeof(W)) : ws;
       }
     }
     ChunkTap* ct = t.ctab + (tb * G + gg) * EC1;
@@ -624,7 +629,6 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
       hyA = hann(hd.dyA, inv_w);
       hyB = hann(hd.dyB, inv_w);
     }
-    bool slow = false;  // some tap of this lane is inside the record but not in the window
 #pragma unroll
     for (int k = 0; k < SH::EC; ++k) {
       T.off0[k] = T.off1[k] = ZERO * int(sizeof(W));
@@ -662,14 +666,12 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
           T.off0[k] = (fast ? wbase + p0 : ZERO) * int(sizeof(W));
           T.off1[k] = (fast ? wbase + p1 : ZERO) * int(sizeof(W));
         }
-        slow |= !fast & (uint32_t(tp.i0) <= uint32_t(S - 2));
+        T.slow |= (!fast & (uint32_t(tp.i0) <= uint32_t(S - 2))) ? (1u << k) : 0u;
       }
       // one element at a time: hoisting the table reads of later elements would hold them all
       // in registers at once
       if constexpr (FS > 1) __builtin_amdgcn_sched_barrier(0);
     }
-    // slow_taps_uni re-derives, lane by lane, which of the chunk's taps those are
-    T.slow = __any(slow) ? ~0u : 0u;
     return T;
   };
   auto make_taps = [&](int c, float& den, int P) {
@@ -695,61 +697,60 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
         const float2 E2 = geo[e];
         const float2 xy = t.exy[e];
         const ElemGeom E{E2.x, E2.y, xy.x - L.olx, xy.y - L.oly};
-        const bool act = lane_ok && e0 + k < a.n_el && in_aperture(ap_F2, a.array_dims, E, r);
-        if (!__any(act)) continue;  // no lane of the wave needs this element
-        float w = 0.0f;
-        if (act) {
-          if (ap_window == USBF_WINDOW_RECT) {
-            w = 1.0f;
-          } else if (a.array_dims == 2) {
-            // separable window: the y factor is kept while consecutive elements share their row
-            // (a wave-uniform branch: skipped unless some lane meets a new row)
-            if (__any(E.dy != hy_dy)) {
-              hy = hann(E.dy, inv_w);
-              hy_dy = E.dy;
+        const int4 wd = t.wnd[e];
+        // lanes outside the aperture keep the zero weights; the block is skipped when the whole
+        // wave is outside
+        if ((e0 + k < a.n_el) & lane_ok & in_aperture(ap_F2, a.array_dims, E, r)) {
+          float w = 1.0f;
+          if (ap_window != USBF_WINDOW_RECT) {
+            if (a.array_dims == 2) {
+              // separable window: the y factor is kept while consecutive elements share their
+              // row (a wave-uniform branch: skipped unless some lane meets a new row)
+              if (__any(E.dy != hy_dy)) {
+                hy = hann(E.dy, inv_w);
+                hy_dy = E.dy;
+              }
+              w = hann(E.dx, inv_w) * hy;
+            } else {
+              w = hann(E.dx, inv_w);
             }
-            w = hann(E.dx, inv_w) * hy;
-          } else {
-            w = hann(E.dx, inv_w);
           }
+          den += w;
+          const Tap tp = fast_tap(a, b, dtx, E.A, E.B, r, r2, rr);
+          // a tap not summed from the window reads the zero vector (its weights need no masking)
+          const float wp = w * tp.phi;
+          T.w1[k] = wp;
+          T.w0[k] = w - wp;
+          const bool fast = on_grp & (uint32_t(tp.i0) - uint32_t(wd.z) < uint32_t(wd.w));
+          const int rel = tp.i0 - (wd.x & ~3);
+          const int wbase = k * ta.span;
+          const bool split = FS > 1 && ta.pshift;
+          const int p0 = split ? ((rel & 1) * half + half_slot(rel >> 1)) : rel;
+          const int p1 = split ? (((rel + 1) & 1) * half + half_slot((rel + 1) >> 1)) : rel + 1;
+          // byte offsets within a buffer
+          T.off0[k] = (fast ? wbase + p0 : ZERO) * int(sizeof(W));
+          T.off1[k] = (fast ? wbase + p1 : ZERO) * int(sizeof(W));
+          T.slow |= (!fast & (uint32_t(tp.i0) <= uint32_t(S - 2))) ? (1u << k) : 0u;
         }
-        den += w;
-        const Tap tp = fast_tap(a, b, dtx, E.A, E.B, r, r2, rr);
-        const bool ok = act && tp.i0 >= 0 && tp.i0 <= S - 2;
-        const float wp = w * tp.phi;
-        T.w1[k] = ok ? wp : 0.0f;
-        T.w0[k] = ok ? w - wp : 0.0f;
-        const int2 wd = t.wnd[e];
-        const int rel = tp.i0 - (wd.x & ~3);
-        const bool in_win = on_grp && (wd.x & 2) && rel >= 0 && tp.i0 + 1 <= wd.y && rel + 1 < ta.span;
-        const int wbase = k * ta.span;
-        const bool split = FS > 1 && ta.pshift;
-        const int p0 = split ? ((rel & 1) * half + half_slot(rel >> 1)) : rel;
-        const int p1 = split ? (((rel + 1) & 1) * half + half_slot((rel + 1) >> 1)) : rel + 1;
-        // byte offsets within a buffer
-        T.off0[k] = ((ok && in_win) ? wbase + p0 : ZERO) * int(sizeof(W));
-        T.off1[k] = ((ok && in_win) ? wbase + p1 : ZERO) * int(sizeof(W));
-        T.slow |= (ok && !in_win) ? (1u << k) : 0u;
       }
       return T;
     }
   };
-  // one-line tiles: T.slow is set when some lane has a tap inside the record but outside the staged
-  // window; each lane re-derives which of its taps those are (from the whole-tile tables)
-  auto slow_taps_uni = [&](const Taps& T, int c, int fb, float* acc) {
+  // Taps inside the record but outside the staged window (unusual geometry only) read global
+  // memory: bit k of T.slow marks this lane's tap of the chunk's element k.
+  auto slow_taps = [&](const Taps& T, int c, int fb, float* acc) {
     const int e0 = c * ta.ec;
     for (int k = 0; k < ta.ec; ++k) {
       if (!(T.slow & (1u << k))) continue;
-      const int e = e0 + k;
-      const ElemGeom E = elem_geom(a, L, e);
-      const bool act = lane_ok && in_aperture(a.F2, a.array_dims, E, r);
-      const Tap tp = fast_tap(a, b, dtx, E.A, E.B, r, r2, rr);
-      const int2 wd = t.wnd[e];
-      const int ws = wd.x & ~3;
-      const bool in_rec = tp.i0 >= 0 && tp.i0 <= S - 2;
-      const bool in_win = on_grp && (wd.x & 2) && tp.i0 >= ws && tp.i0 + 1 <= wd.y && tp.i0 - ws + 1 < ta.span;
-      if (!(act && in_rec && !in_win)) continue;
-      const int16_t* p = own_block + size_t(e) * S + tp.i0;
+      float2 E2;
+      if constexpr (GEO_G) {
+        const ElemGeom E = elem_geom(a, L, e0 + k);
+        E2 = make_float2(E.A, E.B);
+      } else {
+        E2 = geo[e0 + k];
+      }
+      const Tap tp = fast_tap(a, b, dtx, E2.x, E2.y, r, r2, rr);
+      const int16_t* p = own_block + size_t(e0 + k) * S + tp.i0;
       float sw0 = 0.0f, sw1 = 0.0f;
 #pragma unroll
       for (int kk = 0; kk < SH::EC; ++kk)
@@ -761,32 +762,6 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
       for (int f = 0; f < FB; ++f) {
         const int16_t* q = p + size_t(fb + f) * frame_stride;
         acc[f] = __builtin_fmaf(sw0, float(q[0]), __builtin_fmaf(sw1, float(q[1]), acc[f]));
-      }
-    }
-  };
-  // taps outside the staged windows: read global memory
-  auto slow_taps = [&](const Taps& T, int c, int fb, float* acc) {
-    if constexpr (UNI) {
-      slow_taps_uni(T, c, fb, acc);
-    } else {
-      const int e0 = c * ta.ec;
-      for (int k = 0; k < ta.ec; ++k) {
-        if (!(T.slow & (1u << k))) continue;
-        const float2 E2 = geo[e0 + k];
-        const Tap tp = fast_tap(a, b, dtx, E2.x, E2.y, r, r2, rr);
-        const int16_t* p = own_block + size_t(e0 + k) * S + tp.i0;
-        float sw0 = 0.0f, sw1 = 0.0f;
-#pragma unroll
-        for (int kk = 0; kk < SH::EC; ++kk)
-          if (kk == k) {
-            sw0 = T.w0[kk];
-            sw1 = T.w1[kk];
-          }
-#pragma unroll
-        for (int f = 0; f < FB; ++f) {
-          const int16_t* q = p + size_t(fb + f) * frame_stride;
-          acc[f] = __builtin_fmaf(sw0, float(q[0]), __builtin_fmaf(sw1, float(q[1]), acc[f]));
-        }
       }
     }
   };
