@@ -212,9 +212,15 @@ __host__ __device__ constexpr size_t fused_lds_bytes(int M) {
   return (size_t(M + 16) + 2 * fused_buf_elems(M)) * sizeof(__bf16) + 3 * kNC * sizeof(float) + 64;
 }
 
-__device__ inline uint32_t pack_bf16x2(float lo, float hi) {
-  const __bf16 a = __bf16(lo), b = __bf16(hi);
-  return uint32_t(__builtin_bit_cast(uint16_t, a)) | (uint32_t(__builtin_bit_cast(uint16_t, b)) << 16);
+typedef float f32x2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+typedef short i16x2v __attribute__((ext_vector_type(2)));
+// ReLU of two values rounded to bf16 (round to nearest even), packed: one packed conversion and
+// one packed integer max -- a bf16 with the sign bit set is a negative int16, so max(., 0)
+// zeroes it.  Rounding preserves sign and order, so this equals rounding the ReLU.
+__device__ inline uint32_t relu_bf16x2(float lo, float hi) {
+  const bf16x2v v = __builtin_convertvector((f32x2v){lo, hi}, bf16x2v);
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(i16x2v, v), (i16x2v){0, 0}));
 }
 
 template <bool SAVE>
@@ -227,7 +233,7 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(3))
   __bf16* a0 = lds;
   __bf16* bufA = lds + (M + 16);
   __bf16* bufB = bufA + fused_buf_elems(M);
-  float* zb = reinterpret_cast<float*>(bufB + 2 * kRowStride);              // [M][8], bufB past its zero rows
+  float* zt = reinterpret_cast<float*>(bufB + 2 * kRowStride);              // [5][M + 4], bufB past its zero rows
   float* bias = reinterpret_cast<float*>(bufB + fused_buf_elems(M));        // [3][32]
   float* red = bias + 3 * kNC;                                              // [4] sums + [4] flags
   const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
@@ -266,16 +272,29 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(3))
     }
     return acc;
   };
-  // ReLU, bf16 and the four 8-byte stores of a tile's D[co][position] into dst
+  // ReLU, bf16 and the stores of a tile's D[co][position] into dst.  Lane (j, hi) holds
+  // channels 8q + 4 hi .. + 3 of position j for q = 0..3; one exchange with lane j + 32
+  // (v_permlane32_swap: the upper half-wave of the first operand trades places with the lower
+  // half-wave of the second) leaves lane hi = 0 with channels 0..15 and lane hi = 1 with
+  // 16..31, written as two 16-byte stores -- 8-byte stores of consecutive rows kRowStride apart
+  // would meet every bank group twice in a pass (16-byte stores of 8 lanes do not).
   auto store_relu = [&](const f32x16& acc, int mt, __bf16* dst) {
-    __bf16* row = dst + (32 * mt + j + 2) * kRowStride + 4 * hi;
+    uint32_t v[4][2];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      uint2 v;
-      v.x = pack_bf16x2(fmaxf(acc[4 * q + 0], 0.0f), fmaxf(acc[4 * q + 1], 0.0f));
-      v.y = pack_bf16x2(fmaxf(acc[4 * q + 2], 0.0f), fmaxf(acc[4 * q + 3], 0.0f));
-      *reinterpret_cast<uint2*>(row + 8 * q) = v;
+      v[q][0] = relu_bf16x2(acc[4 * q + 0], acc[4 * q + 1]);
+      v[q][1] = relu_bf16x2(acc[4 * q + 2], acc[4 * q + 3]);
     }
+    uint4 o[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const auto s0 = __builtin_amdgcn_permlane32_swap(v[h][0], v[h + 2][0], false, false);
+      const auto s1 = __builtin_amdgcn_permlane32_swap(v[h][1], v[h + 2][1], false, false);
+      o[h] = make_uint4(s0[0], s1[0], s0[1], s1[1]);
+    }
+    __bf16* row = dst + (32 * mt + j + 2) * kRowStride + 16 * hi;
+    *reinterpret_cast<uint4*>(row) = o[0];
+    *reinterpret_cast<uint4*>(row + 8) = o[1];
   };
   // 32 x 32 channel layer from src into dst
   auto layer32 = [&](const __bf16* src, const bf16x8* wk, int layer, __bf16* dst) {
@@ -333,11 +352,23 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(3))
       if constexpr (SAVE) a0g[size_t(p) * M + tid] = v;
     }
     __syncthreads();
-    // layer 1 (one input channel): B[k][position] = a0[position + k - 2] for k < 5
+    // layer 1 (one input channel): B[k][position] = a0[position + k - 2] for k < 5.  Every lane
+    // loads the eight samples a0[p .. p + 7], p = position + 8 hi (two bytes apart, so from
+    // five aligned words with funnel shifts): the packed weights are zero for k >= 5, and the
+    // samples there are finite, so they add nothing.
     for (int mt = wave; mt < n_mt; mt += kFwdThreads / 64) {
-      bf16x8 b;
+      const int p = 32 * mt + j + 8 * hi;
+      const uint32_t* m = reinterpret_cast<const uint32_t*>(a0) + (p >> 1);
+      const uint32_t sh = (p & 1) * 16;
+      uint32_t d[5];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) b[e] = (hi == 0 && e < kKS) ? a0[32 * mt + j + e] : __bf16(0.0f);
+      for (int k = 0; k < 5; ++k) d[k] = m[k];
+      uint4 bw;
+      bw.x = __builtin_amdgcn_alignbit(d[1], d[0], sh);
+      bw.y = __builtin_amdgcn_alignbit(d[2], d[1], sh);
+      bw.z = __builtin_amdgcn_alignbit(d[3], d[2], sh);
+      bw.w = __builtin_amdgcn_alignbit(d[4], d[3], sh);
+      const bf16x8 b = __builtin_bit_cast(bf16x8, bw);
       const f32x16 acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w1, b, bias_init(0), 0, 0, 0);
       store_relu(acc, mt, bufA);
     }
@@ -357,22 +388,24 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(3))
         const bf16x8 b = *reinterpret_cast<const bf16x8*>(bufA + (32 * mt + j + 2) * kRowStride + 16 * s + 8 * hi);
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w4[s], b, acc, 0, 0, 0);
       }
-      float* zr = zb + (32 * mt + j) * 8;
-      if (hi == 0)
-        *reinterpret_cast<float4*>(zr) = float4{acc[0], acc[1], acc[2], acc[3]};
-      else
-        zr[4] = acc[0];
+      // Z[t][position] at zt[t][position + 2]: consecutive lanes write consecutive words
+      float* zc = zt + 32 * mt + j + 2;
+      if (hi == 0) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) zc[t * (M + 4)] = acc[t];
+      } else {
+        zc[4 * (M + 4)] = acc[0];
+      }
     }
+    // the two words before and after each row are zero (layer 2 used this memory)
+    if (tid < 4 * kKS) zt[(tid / 4) * (M + 4) + ((tid & 3) < 2 ? (tid & 3) : M + (tid & 3))] = 0.0f;
     __syncthreads();
     float wm = 0.0f;
     if (tid < M) {
       // w[m] = b4 + sum_t Z[t][m + t - 2] (positions outside the pixel contribute 0)
       float s = 0.0f;
 #pragma unroll
-      for (int t = 0; t < kKS; ++t) {
-        const int q = tid + t - 2;
-        if (q >= 0 && q < M) s += zb[q * 8 + t];
-      }
+      for (int t = 0; t < kKS; ++t) s += zt[t * (M + 4) + tid + t];
       wm = s + b4;
       if (w) w[size_t(p) * M + tid] = wm;
     }
