@@ -683,57 +683,73 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
         return uni_taps(std::integral_constant<int, 2>{}, ct, den);
       return uni_taps(std::integral_constant<int, 3>{}, ct, den);
     } else {
-      Taps T;
-      T.slow = 0u;
-      // the chunk is the same for every lane: make that visible, so element data comes
-      // through scalar loads
-      const int e0 = __builtin_amdgcn_readfirstlane(c * ta.ec);
+      // window and array kind as compile-time cases where they are the same for the whole
+      // launch (case 0: read per slot at run time, for apodization sets)
+      auto gen_taps = [&](auto mode_) {
+        constexpr int MODE = decltype(mode_)::value;  // 1, 2: Hann; 3, 4: rect; 2, 4: matrix arrays
+        const bool hann_w = MODE == 0 ? ap_window != USBF_WINDOW_RECT : MODE <= 2;
+        const int dims = MODE == 0 ? a.array_dims : (MODE == 2 || MODE == 4) ? 2 : 1;
+        Taps T;
+        T.slow = 0u;
+        // the chunk is the same for every lane: make that visible, so element data comes
+        // through scalar loads
+        const int e0 = __builtin_amdgcn_readfirstlane(c * ta.ec);
 #pragma unroll
-      for (int k = 0; k < SH::EC; ++k) {
-        T.off0[k] = T.off1[k] = ZERO * int(sizeof(W));
-        T.w0[k] = T.w1[k] = 0.0f;
-        if (k >= ta.ec) continue;
-        const int e = min(e0 + k, a.n_el - 1);
-        const float2 E2 = geo[e];
-        const float2 xy = t.exy[e];
-        const ElemGeom E{E2.x, E2.y, xy.x - L.olx, xy.y - L.oly};
-        const int4 wd = t.wnd[e];
-        // lanes outside the aperture keep the zero weights; the block is skipped when the whole
-        // wave is outside
-        if ((e0 + k < a.n_el) & lane_ok & in_aperture(ap_F2, a.array_dims, E, r)) {
-          float w = 1.0f;
-          if (ap_window != USBF_WINDOW_RECT) {
-            if (a.array_dims == 2) {
-              // separable window: the y factor is kept while consecutive elements share their
-              // row (a wave-uniform branch: skipped unless some lane meets a new row)
-              if (__any(E.dy != hy_dy)) {
-                hy = hann(E.dy, inv_w);
-                hy_dy = E.dy;
+        for (int k = 0; k < SH::EC; ++k) {
+          T.off0[k] = T.off1[k] = ZERO * int(sizeof(W));
+          T.w0[k] = T.w1[k] = 0.0f;
+          if (k >= ta.ec) continue;
+          const int e = min(e0 + k, a.n_el - 1);
+          const float2 E2 = geo[e];
+          const float2 xy = t.exy[e];
+          const ElemGeom E{E2.x, E2.y, xy.x - L.olx, dims == 2 ? xy.y - L.oly : 0.0f};
+          const int4 wd = t.wnd[e];
+          // lanes outside the aperture keep the zero weights; the block is skipped when the
+          // whole wave is outside
+          if ((e0 + k < a.n_el) & lane_ok & in_aperture(ap_F2, dims, E, r)) {
+            float w = 1.0f;
+            if (hann_w) {
+              if (dims == 2) {
+                // separable window: the y factor is kept while consecutive elements share their
+                // row (a wave-uniform branch: skipped unless some lane meets a new row)
+                if (__any(E.dy != hy_dy)) {
+                  hy = hann(E.dy, inv_w);
+                  hy_dy = E.dy;
+                }
+                w = hann(E.dx, inv_w) * hy;
+              } else {
+                w = hann(E.dx, inv_w);
               }
-              w = hann(E.dx, inv_w) * hy;
-            } else {
-              w = hann(E.dx, inv_w);
             }
+            den += w;
+            const Tap tp = fast_tap(a, b, dtx, E.A, E.B, r, r2, rr);
+            // a tap not summed from the window reads the zero vector (its weights need no
+            // masking)
+            const float wp = w * tp.phi;
+            T.w1[k] = wp;
+            T.w0[k] = w - wp;
+            const bool fast = on_grp & (uint32_t(tp.i0) - uint32_t(wd.z) < uint32_t(wd.w));
+            const int rel = tp.i0 - (wd.x & ~3);
+            const int wbase = k * ta.span;
+            const bool split = FS > 1 && ta.pshift;
+            const int p0 = split ? ((rel & 1) * half + half_slot(rel >> 1)) : rel;
+            const int p1 = split ? (((rel + 1) & 1) * half + half_slot((rel + 1) >> 1)) : rel + 1;
+            // byte offsets within a buffer
+            T.off0[k] = (fast ? wbase + p0 : ZERO) * int(sizeof(W));
+            T.off1[k] = (fast ? wbase + p1 : ZERO) * int(sizeof(W));
+            T.slow |= (!fast & (uint32_t(tp.i0) <= uint32_t(S - 2))) ? (1u << k) : 0u;
           }
-          den += w;
-          const Tap tp = fast_tap(a, b, dtx, E.A, E.B, r, r2, rr);
-          // a tap not summed from the window reads the zero vector (its weights need no masking)
-          const float wp = w * tp.phi;
-          T.w1[k] = wp;
-          T.w0[k] = w - wp;
-          const bool fast = on_grp & (uint32_t(tp.i0) - uint32_t(wd.z) < uint32_t(wd.w));
-          const int rel = tp.i0 - (wd.x & ~3);
-          const int wbase = k * ta.span;
-          const bool split = FS > 1 && ta.pshift;
-          const int p0 = split ? ((rel & 1) * half + half_slot(rel >> 1)) : rel;
-          const int p1 = split ? (((rel + 1) & 1) * half + half_slot((rel + 1) >> 1)) : rel + 1;
-          // byte offsets within a buffer
-          T.off0[k] = (fast ? wbase + p0 : ZERO) * int(sizeof(W));
-          T.off1[k] = (fast ? wbase + p1 : ZERO) * int(sizeof(W));
-          T.slow |= (!fast & (uint32_t(tp.i0) <= uint32_t(S - 2))) ? (1u << k) : 0u;
         }
+        return T;
+      };
+      if constexpr (SETS) {
+        return gen_taps(std::integral_constant<int, 0>{});
+      } else {
+        const bool d2 = a.array_dims == 2;
+        if (a.window != USBF_WINDOW_RECT)
+          return d2 ? gen_taps(std::integral_constant<int, 2>{}) : gen_taps(std::integral_constant<int, 1>{});
+        return d2 ? gen_taps(std::integral_constant<int, 4>{}) : gen_taps(std::integral_constant<int, 3>{});
       }
-      return T;
     }
   };
   // Taps inside the record but outside the staged window (unusual geometry only) read global
