@@ -202,14 +202,13 @@ __global__ __launch_bounds__(kNetThreads) void conv_kernel(const __bf16* __restr
 // LDS: a0 [M + 16] bf16 (position m at index m + 2, zeros around); two buffers of M + 4 rows
 // of kRowStride bf16 (position m at row m + 2; rows 0, 1, M + 2, M + 3 stay zero; 32 channels
 // and 8 bf16 of padding, so that the 16-byte operand reads of consecutive positions spread
-// over the banks); the output layer's Z [M][8] float in the second buffer; biases; the
-// cross-wave sums.
+// over the banks); the output layer's Z [5][M + 4] float in the second buffer; biases.
 constexpr int kFwdThreads = 256;
 constexpr int kRowStride = kNC + 8;
 
 __host__ __device__ constexpr size_t fused_buf_elems(int M) { return size_t(M + 4) * kRowStride; }
 __host__ __device__ constexpr size_t fused_lds_bytes(int M) {
-  return (size_t(M + 16) + 2 * fused_buf_elems(M)) * sizeof(__bf16) + 3 * kNC * sizeof(float) + 64;
+  return (size_t(M + 16) + 2 * fused_buf_elems(M)) * sizeof(__bf16) + 3 * kNC * sizeof(float);
 }
 
 typedef float f32x2v __attribute__((ext_vector_type(2)));
@@ -235,7 +234,6 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(3))
   __bf16* bufB = bufA + fused_buf_elems(M);
   float* zt = reinterpret_cast<float*>(bufB + 2 * kRowStride);              // [5][M + 4], bufB past its zero rows
   float* bias = reinterpret_cast<float*>(bufB + fused_buf_elems(M));        // [3][32]
-  float* red = bias + 3 * kNC;                                              // [4] sums + [4] flags
   const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
   const int j = lane % 32, hi = lane / 32;
   const int n_mt = M / 32;
@@ -323,25 +321,15 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(3))
 #pragma unroll
     for (int k = 0; k < 4; ++k) xr[k] = (lane + 64 * k < M) ? xp[lane + 64 * k] : 0.0f;
   };
-  // y of pixel q from the waves' partial sums in red
-  auto finish_y = [&](int q) {
-    float acc = 0.0f;
-    int bad = 0;
-    for (int v = 0; v < (M + 63) / 64; ++v) {
-      acc += red[v];
-      bad |= reinterpret_cast<const int*>(red)[4 + v];
-    }
-    y[q] = (bad && fallback) ? fallback[q] : acc;
-  };
   if (int(blockIdx.x) < n_pix) load_x(blockIdx.x);
   for (int p = blockIdx.x; p < n_pix; p += gridDim.x) {
-    __syncthreads();  // the previous pixel is done with a0, the buffers and the sums
-    if (y && tid == 0 && p != int(blockIdx.x)) finish_y(p - gridDim.x);
-    float ss = 0.0f, xm = 0.0f;
+    __syncthreads();  // the previous pixel is done with a0 and the buffers
+    float ss = 0.0f, xm = 0.0f, xc[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       ss = __builtin_fmaf(xr[k], xr[k], ss);
       xm = (k == wave) ? xr[k] : xm;  // position tid = lane + 64 wave
+      if constexpr (!SAVE) xc[k] = xr[k];  // kept past the prefetch of the next pixel (for y)
     }
     for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off, 64);
     const float inv = 1.0f / sqrtf(ss / float(M) + 1e-12f);
@@ -409,24 +397,29 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(3))
       wm = s + b4;
       if (w) w[size_t(p) * M + tid] = wm;
     }
-    if (y) {
-      // per-wave partial sums; thread 0 combines them after the next barrier (at the top of the
-      // next pixel, or after the loop), so the weighted sum costs no barrier of its own
-      float acc = tid < M ? wm * xm : 0.0f;
-      int bad = tid < M && !(fabsf(wm) < INFINITY);
+    if (!SAVE && y && wave == kFwdThreads / 64 - 1) {
+      // the last wave (which holds no position for M <= 192) forms y = sum_m w[m] x[m] alone:
+      // it has every sample of the pixel and re-forms the weights from Z exactly as above
+      float acc = 0.0f;
+      int bad = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int m = lane + 64 * k;
+        if (m < M) {
+          float s = 0.0f;
+#pragma unroll
+          for (int t = 0; t < kKS; ++t) s += zt[t * (M + 4) + m + t];
+          const float wk = s + b4;
+          acc = __builtin_fmaf(wk, xc[k], acc);
+          bad |= !(fabsf(wk) < INFINITY);
+        }
+      }
       for (int off = 32; off > 0; off >>= 1) {
         acc += __shfl_xor(acc, off, 64);
         bad |= __shfl_xor(bad, off, 64);
       }
-      if (lane == 0) {
-        red[wave] = acc;
-        reinterpret_cast<int*>(red)[4 + wave] = bad;
-      }
+      if (lane == 0) y[p] = (bad && fallback) ? fallback[p] : acc;
     }
-  }
-  if (y && int(blockIdx.x) < n_pix) {
-    __syncthreads();
-    if (tid == 0) finish_y(n_pix - 1 - (n_pix - 1 - int(blockIdx.x)) % int(gridDim.x));
   }
 }
 
@@ -696,8 +689,8 @@ static int fused_grid(int n_pix, size_t lds) {
   return std::max(1, std::min(n_pix, per_cu * n_cu));
 }
 
-// forward pass; with `save` the layer inputs go to the workspace for the backward pass; with
-// y the weighted sum is formed as well (w may then be null)
+// forward pass; with `save` the layer inputs go to the workspace for the backward pass; without,
+// y (if given) receives the weighted sum as well (w may then be null)
 static void net_forward(const NetState& st, const float* x, int n_pix, int M, const NetWs& w, bool save,
                         hipStream_t s, const float* fallback = nullptr, float* y = nullptr) {
   const size_t lds = fused_lds_bytes(M);
