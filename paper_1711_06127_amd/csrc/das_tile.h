@@ -177,8 +177,8 @@ __host__ __device__ constexpr size_t ctab_bytes() {
   return line_per_wave<G, FS, SETS>() ? 2 * size_t(G) * (Shape<G, FS>::EC + 1) * sizeof(ChunkTap) : 0;
 }
 
-// per-(line, element) receive constants and element positions (one-line tiles derive them from
-// the geometry arrays when they tabulate a chunk instead)
+// per-(line, element) receive constants and element positions (geo_from_global tiles derive
+// them from the geometry arrays when they tabulate a chunk instead)
 template <int G, int FS>
 __host__ __device__ constexpr size_t geo_entries(int n_el) {
   return geo_from_global<G, FS>() ? 0 : size_t(G + 1) * n_el;
@@ -615,10 +615,10 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
       *reinterpret_cast<ChunkHdr*>(ct + SH::EC) = h;
     }
   };
-  // taps of a line_per_wave tile from the table of the wave's line.  MODE (chosen per chunk, wave-uniform): 0 rect
-  // window, 1 Hann over x, 2 separable Hann whose chunk spans at most two y offsets (the y factors
-  // computed once per chunk), 3 separable Hann in general (the y factor kept while the offset
-  // repeats).
+  // taps of a line_per_wave tile from the table of the wave's line.  MODE (chosen per chunk,
+  // wave-uniform): 0 rect window, 1 Hann over x, 2 separable Hann whose chunk spans at most two
+  // y offsets (the y factors computed once per chunk), 3 separable Hann in general (the y factor
+  // kept while the offset repeats).
   auto uni_taps = [&](auto mode_, const ChunkTap* ct, float& den) {
     constexpr int MODE = decltype(mode_)::value;
     Taps T;
