@@ -135,7 +135,7 @@ struct alignas(16) ChunkTap {
 struct alignas(16) ChunkHdr {
   float dyA, dyB;
   int two;  // every element's y offset is dyA or dyB
-  int pad;
+  int one;  // every element's y offset is dyA
 };
 static_assert(sizeof(ChunkHdr) <= sizeof(ChunkTap), "the header takes one table entry");
 
@@ -158,9 +158,11 @@ struct TileLds {
   float2* exy;                // [n_el]: element x, y (lateral offsets are taken from the lines)
   LineGeom* lines;            // [G]
   int4* wnd;                  // [n_el]: (lo | flags, hi, flo, fn); lo a multiple of 4, flags bit 0
-                              // needed, bit 1 staged; taps i0 in [flo, flo + fn) are summed from
-                              // the staged window (inside the record, the window and its span)
-  int* flg;                   // [(n_el + 3) / 4]: the flags, a byte per element, while they are built
+                              // needed, bit 1 staged; hi the last sample to stage (INT_MIN when
+                              // none is); taps i0 in [flo, flo + fn) are summed from the staged
+                              // window (inside the record, the window and its span)
+  int* flg;                   // [(n_el + 3) / 4]: the flags, a byte per element, while they are
+                              // built; then a byte per chunk: some element of it is needed
 };
 
 // two staging buffers, each followed by two all-zero frame vectors (kept zero for the whole
@@ -276,22 +278,21 @@ __device__ inline Items<IPT> chunk_items(const TileLds<G, FS>& t, const TileArgs
   const int e0S = e0 * S;
 #pragma unroll
   for (int it = 0; it < IPT; ++it) {
-    const int k = sl.k[it], e = e0 + k;
-    d.voff[it] = 0u;
-    d.dst[it] = -1;
-    if (k >= ec || c < 0) continue;
-    const int4 wd = t.wnd[e];
+    const int k = sl.k[it];
+    const bool ok = (c >= 0) & (k < ec);
+    // the window's start and its last needed sample (INT_MIN when nothing is staged)
+    const int2 wd = *reinterpret_cast<const int2*>(&t.wnd[ok ? e0 + k : 0]);
     const int i = (wd.x & ~3) + sl.q4[it];
-    if (!(wd.x & 2) || i > wd.y) continue;
+    const bool take = ok & (i <= wd.y);
     // A quad with no sample inside the record loads the record's first samples instead:
     // windows reach past either end of the record for deep pixels at the edge of the aperture.
     // Window starts are multiples of 4, so a quad that starts before the record lies wholly
     // before it; a quad that reaches past the end starts inside it (i < S), and its samples
     // beyond the end are clamped in issue_stage (VEC: S % 4 == 0, the quad is wholly inside).
     // Every load therefore stays inside element e's record.
-    const int ic = (i >= 0 && i < S) ? i : 0;
-    d.voff[it] = uint32_t(e0S + sl.kS[it] + ic) * uint32_t(sizeof(int16_t));
-    d.dst[it] = sl.dst[it];
+    const int ic = uint32_t(i) < uint32_t(S) ? i : 0;
+    d.voff[it] = take ? uint32_t(e0S + sl.kS[it] + ic) * uint32_t(sizeof(int16_t)) : 0u;
+    d.dst[it] = take ? sl.dst[it] : -1;
   }
   return d;
 }
@@ -481,7 +482,16 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
       const int fhi = min(min(hi - 1, lo4 + ta.span - 2), S - 2);
       fn = fhi >= flo ? fhi - flo + 1 : 0;
     }
-    t.wnd[e] = make_int4(lo4 | f, hi, flo, fn);
+    t.wnd[e] = make_int4(lo4 | f, (f & 2) ? hi : INT_MIN, flo, fn);
+  }
+  __syncthreads();
+  // a byte per chunk, in the flags' space: does any of its elements need beamforming
+  const int n_chunks = (a.n_el + ta.ec - 1) / ta.ec;
+  uint8_t* const cneed = reinterpret_cast<uint8_t*>(t.flg);
+  for (int c = tid; c < n_chunks; c += kDasThreads) {
+    int any = 0;
+    for (int k = 0; k < ta.ec && c * ta.ec + k < a.n_el; ++k) any |= t.wnd[c * ta.ec + k].x & 3;
+    cneed[c] = any != 0;
   }
   __syncthreads();
 
@@ -503,17 +513,11 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
   const int16_t* grp_block = rf + size_t(t_grp < 0 ? 0 : t_grp) * tx_block;
   const int16_t* own_block = rf + size_t(L.tx < 0 ? 0 : L.tx) * tx_block;
   const float2* geo = t.geo + g * a.n_el;
-  const int n_chunks = (a.n_el + ta.ec - 1) / ta.ec;
   const int half = ta.span >> 1;
 
-  auto chunk_needed = [&](int c) {
-    int any = 0;
-    for (int k = 0; k < ta.ec && c * ta.ec + k < a.n_el; ++k) any |= t.wnd[c * ta.ec + k].x & 3;
-    return any != 0;
-  };
   auto next_chunk = [&](int c) {
     for (++c; c < n_chunks; ++c)
-      if (chunk_needed(c)) return c;
+      if (cneed[c]) return c;
     return n_chunks;
   };
   const uint32_t fbytes = uint32_t(std::min<uint64_t>(frame_stride * sizeof(int16_t), 0xffffffffull));
@@ -535,6 +539,7 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
   struct Taps {
     int off0[SH::EC], off1[SH::EC];
     float w0[SH::EC], w1[SH::EC];
+    float scale;  // line_per_wave tiles: a factor common to the chunk's weights
     uint32_t slow;
   };
   // taps of this lane's pixel for chunk c, shared by every frame; a tap that contributes
@@ -611,34 +616,57 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
       h.dyA = dyA;
       h.dyB = dyB;
       h.two = two;
-      h.pad = 0;
+      h.one = other == 0;
       *reinterpret_cast<ChunkHdr*>(ct + SH::EC) = h;
     }
   };
   // taps of a line_per_wave tile from the table of the wave's line.  MODE (chosen per chunk,
   // wave-uniform): 0 rect window, 1 Hann over x, 2 separable Hann whose chunk spans at most two
   // y offsets (the y factors computed once per chunk), 3 separable Hann in general (the y factor
-  // kept while the offset repeats).
+  // kept while the offset repeats), 4 separable Hann whose chunk lies on one y offset (its y
+  // factor is the chunk's common factor T.scale, applied to the chunk's sums and to its share
+  // of the weight total instead of to every weight).  An element is evaluated by the whole wave as soon as one
+  // lane has it inside its aperture (masking the others off would save no issue cycles); the
+  // lanes outside take weight zero.  Single-frame tiles keep the weight and the fraction of
+  // each tap (the sum interpolates, then weights); multi-frame tiles keep the two tap weights.
+  // T.slow is set in the lanes that have some tap inside the record but outside the staged
+  // window (slow_taps_uni finds which).
+  const uint64_t lane_mask = __builtin_amdgcn_ballot_w64(lane_ok);
   auto uni_taps = [&](auto mode_, const ChunkTap* ct, float& den) {
     constexpr int MODE = decltype(mode_)::value;
     Taps T;
-    T.slow = 0u;
+    bool slow = false;
     const ChunkHdr hd = *reinterpret_cast<const ChunkHdr*>(ct + SH::EC);
     float hyA = 1.0f, hyB = 1.0f;
-    if constexpr (MODE == 2) {
-      hyA = hann(hd.dyA, inv_w);
-      hyB = hann(hd.dyB, inv_w);
-    }
+    if constexpr (MODE == 2 || MODE == 4) hyA = hann(hd.dyA, inv_w);
+    if constexpr (MODE == 2) hyB = hann(hd.dyB, inv_w);
+    T.scale = MODE == 4 ? hyA : 1.0f;
+    float pden = 0.0f;  // the chunk's weights, before T.scale
 #pragma unroll
     for (int k = 0; k < SH::EC; ++k) {
-      T.off0[k] = T.off1[k] = ZERO * int(sizeof(W));
-      T.w0[k] = T.w1[k] = 0.0f;
-      if (k >= ta.ec) continue;
-      const ChunkTap& x = ct[k];
+      // (the zero taps are set where the element is skipped: set ahead, they would cost two
+      // moves per element)
+      if (k >= ta.ec) {
+        T.off0[k] = T.off1[k] = ZERO * int(sizeof(W));
+        T.w0[k] = T.w1[k] = 0.0f;
+        continue;
+      }
+      // the entry in two 16-byte reads (taken apart, its fields would be read one by one
+      // inside branches)
+      const float4 xg = *reinterpret_cast<const float4*>(ct + k);
+      const int4 xw = *reinterpret_cast<const int4*>(reinterpret_cast<const char*>(ct + k) + 16);
+      ChunkTap x;
+      x.A = xg.x;
+      x.B = xg.y;
+      x.dx = xg.z;
+      x.dy = xg.w;
+      x.thr = __int_as_float(xw.x);
+      x.base = xw.y;
+      x.lo = xw.z;
+      x.n = xw.w;
       const float dy = x.dy;
-      // lanes outside the aperture keep the zero weights; the block is skipped when the whole
-      // wave is outside
-      if ((x.thr <= r) & lane_ok) {
+      const bool inside = (x.thr <= r) & lane_ok;
+      if ((__builtin_amdgcn_ballot_w64(x.thr <= r) & lane_mask) != 0) {
         float w = 1.0f;
         if constexpr (MODE >= 1) w = hann(x.dx, inv_w);
         if constexpr (MODE == 2) w *= dy == hd.dyA ? hyA : hyB;
@@ -649,11 +677,17 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
           }
           w *= hy;
         }
-        den += w;
+        w = inside ? w : 0.0f;
+        pden += w;
         const Tap tp = fast_tap(a, b, dtx, x.A, x.B, r, r2, rr);
-        const float wp = w * tp.phi;
-        T.w1[k] = wp;
-        T.w0[k] = w - wp;
+        if constexpr (FS == 1) {
+          T.w0[k] = w;
+          T.w1[k] = tp.phi;
+        } else {
+          const float wp = w * tp.phi;
+          T.w1[k] = wp;
+          T.w0[k] = w - wp;
+        }
         // a tap not summed from the window reads the zero vector (its weights need no masking)
         const uint32_t d = uint32_t(tp.i0) - uint32_t(x.lo);
         const bool fast = d < uint32_t(x.n);
@@ -666,12 +700,17 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
           T.off0[k] = (fast ? wbase + p0 : ZERO) * int(sizeof(W));
           T.off1[k] = (fast ? wbase + p1 : ZERO) * int(sizeof(W));
         }
-        T.slow |= (!fast & (uint32_t(tp.i0) <= uint32_t(S - 2))) ? (1u << k) : 0u;
+        slow |= inside & !fast & (uint32_t(tp.i0) <= uint32_t(S - 2));
+      } else {
+        T.off0[k] = T.off1[k] = ZERO * int(sizeof(W));
+        T.w0[k] = T.w1[k] = 0.0f;
       }
       // one element at a time: hoisting the table reads of later elements would hold them all
       // in registers at once
       if constexpr (FS > 1) __builtin_amdgcn_sched_barrier(0);
     }
+    T.slow = slow ? 1u : 0u;
+    den = __builtin_fmaf(T.scale, pden, den);
     return T;
   };
   auto make_taps = [&](int c, float& den, int P) {
@@ -679,8 +718,9 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
       const ChunkTap* ct = t.ctab + (P * G + g) * EC1;
       if (ap_window == USBF_WINDOW_RECT) return uni_taps(std::integral_constant<int, 0>{}, ct, den);
       if (a.array_dims != 2) return uni_taps(std::integral_constant<int, 1>{}, ct, den);
-      if (reinterpret_cast<const ChunkHdr*>(ct + SH::EC)->two)
-        return uni_taps(std::integral_constant<int, 2>{}, ct, den);
+      const ChunkHdr* hd = reinterpret_cast<const ChunkHdr*>(ct + SH::EC);
+      if (hd->one) return uni_taps(std::integral_constant<int, 4>{}, ct, den);
+      if (hd->two) return uni_taps(std::integral_constant<int, 2>{}, ct, den);
       return uni_taps(std::integral_constant<int, 3>{}, ct, den);
     } else {
       // window and array kind as compile-time cases where they are the same for the whole
@@ -691,6 +731,7 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
         const int dims = MODE == 0 ? a.array_dims : (MODE == 2 || MODE == 4) ? 2 : 1;
         Taps T;
         T.slow = 0u;
+        T.scale = 1.0f;
         // the chunk is the same for every lane: make that visible, so element data comes
         // through scalar loads
         const int e0 = __builtin_amdgcn_readfirstlane(c * ta.ec);
@@ -753,7 +794,39 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
     }
   };
   // Taps inside the record but outside the staged window (unusual geometry only) read global
-  // memory: bit k of T.slow marks this lane's tap of the chunk's element k.
+  // memory.  line_per_wave tiles: the lanes with T.slow set re-derive their taps of the chunk
+  // from its table (the same operations, so the same index) and read those that are neither
+  // staged nor outside the record.
+  auto slow_taps_uni = [&](const Taps& T, const ChunkTap* ct, int c, int fb, float* acc) {
+    const int e0 = c * ta.ec;
+    for (int k = 0; k < ta.ec; ++k) {
+      const ChunkTap& x = ct[k];
+      if (!((x.thr <= r) & lane_ok)) continue;
+      const Tap tp = fast_tap(a, b, dtx, x.A, x.B, r, r2, rr);
+      if ((uint32_t(tp.i0) - uint32_t(x.lo) < uint32_t(x.n)) | (uint32_t(tp.i0) > uint32_t(S - 2))) continue;
+      float sw0 = 0.0f, sw1 = 0.0f;
+#pragma unroll
+      for (int kk = 0; kk < SH::EC; ++kk)
+        if (kk == k) {
+          sw0 = T.w0[kk];
+          sw1 = T.w1[kk];
+        }
+      if constexpr (FS == 1) {  // weight and fraction
+        const float wp = sw0 * sw1;
+        sw1 = wp;
+        sw0 = sw0 - wp;
+      }
+      sw0 *= T.scale;
+      sw1 *= T.scale;
+      const int16_t* p = own_block + size_t(e0 + k) * S + tp.i0;
+#pragma unroll
+      for (int f = 0; f < FB; ++f) {
+        const int16_t* q = p + size_t(fb + f) * frame_stride;
+        acc[f] = __builtin_fmaf(sw0, float(q[0]), __builtin_fmaf(sw1, float(q[1]), acc[f]));
+      }
+    }
+  };
+  // Other tiles: bit k of T.slow marks this lane's tap of the chunk's element k.
   auto slow_taps = [&](const Taps& T, int c, int fb, float* acc) {
     const int e0 = c * ta.ec;
     for (int k = 0; k < ta.ec; ++k) {
@@ -795,19 +868,43 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
     auto sum_stage = [&](const Taps& T, int buf, auto s_) {
       constexpr int s = decltype(s_)::value;
       const char* w = reinterpret_cast<const char*>(t.win + buf * SH::BSTRIDE);
+      if constexpr (UNI) {
+        // the chunk summed on its own, then added times T.scale
+        float part[FS];
 #pragma unroll
-      for (int k = 0; k < SH::EC; ++k) {
-        // the zero vector sits after both buffers: index relative to this buffer
-        if constexpr (FS == 1) {
-          const int16_t* p = reinterpret_cast<const int16_t*>(w + T.off0[k]);
-          acc[s] = __builtin_fmaf(T.w0[k], float(p[0]), __builtin_fmaf(T.w1[k], float(p[1]), acc[s]));
-        } else {
-          const V x0 = *reinterpret_cast<const V*>(w + T.off0[k]);
-          const V x1 = *reinterpret_cast<const V*>(w + T.off1[k]);
+        for (int f = 0; f < FS; ++f) part[f] = 0.0f;
 #pragma unroll
-          for (int f = 0; f < FS; ++f)
-            acc[s * FS + f] = __builtin_fmaf(T.w0[k], FVec<FS>::get(x0, f),
-                                             __builtin_fmaf(T.w1[k], FVec<FS>::get(x1, f), acc[s * FS + f]));
+        for (int k = 0; k < SH::EC; ++k) {
+          if constexpr (FS == 1) {  // weight and fraction: interpolate, then weight
+            const int16_t* p = reinterpret_cast<const int16_t*>(w + T.off0[k]);
+            const float x0 = float(p[0]), x1 = float(p[1]);
+            part[0] = __builtin_fmaf(T.w0[k], __builtin_fmaf(T.w1[k], x1 - x0, x0), part[0]);
+          } else {
+            const V x0 = *reinterpret_cast<const V*>(w + T.off0[k]);
+            const V x1 = *reinterpret_cast<const V*>(w + T.off1[k]);
+#pragma unroll
+            for (int f = 0; f < FS; ++f)
+              part[f] = __builtin_fmaf(T.w0[k], FVec<FS>::get(x0, f),
+                                       __builtin_fmaf(T.w1[k], FVec<FS>::get(x1, f), part[f]));
+          }
+        }
+#pragma unroll
+        for (int f = 0; f < FS; ++f) acc[s * FS + f] = __builtin_fmaf(T.scale, part[f], acc[s * FS + f]);
+      } else {
+#pragma unroll
+        for (int k = 0; k < SH::EC; ++k) {
+          // the zero vector sits after both buffers: index relative to this buffer
+          if constexpr (FS == 1) {
+            const int16_t* p = reinterpret_cast<const int16_t*>(w + T.off0[k]);
+            acc[s] = __builtin_fmaf(T.w0[k], float(p[0]), __builtin_fmaf(T.w1[k], float(p[1]), acc[s]));
+          } else {
+            const V x0 = *reinterpret_cast<const V*>(w + T.off0[k]);
+            const V x1 = *reinterpret_cast<const V*>(w + T.off1[k]);
+#pragma unroll
+            for (int f = 0; f < FS; ++f)
+              acc[s * FS + f] = __builtin_fmaf(T.w0[k], FVec<FS>::get(x0, f),
+                                               __builtin_fmaf(T.w1[k], FVec<FS>::get(x1, f), acc[s * FS + f]));
+          }
         }
       }
       // pin this stage's sums here: otherwise the accumulation may be sunk below later stages,
@@ -848,7 +945,11 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
           if constexpr (GEO_G) ep_next = load_ep(cnn);  // consumed at the end of the next step
         }
         __syncthreads();
-        if (T.slow) slow_taps(T, c, fb, acc);
+        if constexpr (UNI) {
+          if (T.slow) slow_taps_uni(T, t.ctab + (P * G + g) * EC1, c, fb, acc);
+        } else {
+          if (T.slow) slow_taps(T, c, fb, acc);
+        }
         c = cn;
         cn = cnn;
         items_n = items_nn;
@@ -892,7 +993,11 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
         };
         static_for<NS>(step);
         tb ^= 1;
-        if (T.slow) slow_taps(T, c, fb, acc);
+        if constexpr (UNI) {
+          if (T.slow) slow_taps_uni(T, t.ctab + ((tb ^ 1) * G + g) * EC1, c, fb, acc);
+        } else {
+          if (T.slow) slow_taps(T, c, fb, acc);
+        }
         items = next_items;
         c = cn;
       }

@@ -151,7 +151,9 @@ __device__ inline Tap delay_tap(const DasArgs& a, int32_t b, float dtx, float dr
 // The same tap, computed with the hardware square root and reciprocal (each within 1 ulp)
 // instead of the correctly rounded ones, and with the constant part of the delay folded into
 // one fused multiply-add: d = fma(K, drx, K dtx - T0).  q and X are formed exactly as the rule
-// forms them, so their rounding is common to both.  With u = 2^-24 and first-order terms:
+// forms them, so their rounding is common to both; X is not clamped at zero (a negative X, from
+// rounding where the element is at the pixel, gives a NaN, and a NaN takes the rule below).
+// With u = 2^-24 and first-order terms:
 //   |drx_fast - drx_rule| <= 9 u |drx|   (3u for the rule's sqrt/add/divide, 6u for the fast
 //                                         sqrt/add/reciprocal/multiply)
 //   rule, after drx       <= u (2 K |D| + |d|)          (D = dtx + drx, d = K D - T0)
@@ -159,13 +161,12 @@ __device__ inline Tap delay_tap(const DasArgs& a, int32_t b, float dtx, float dr
 // so |d_fast - d_rule| <= u (K (13 |drx| + 6 |dtx|) + 3 |T0|).  Twice that is the guard band:
 // outside it floor(d_fast) = floor(d_rule) and the fast value is kept (the fraction then
 // differs from the rule's by less than the band); inside it -- or where the fast value is not
-// finite (r = 0 and the element on the line's origin) -- the rule itself is evaluated.  The
-// integer index is therefore always the rule's.
+// finite (X < 0, or r = 0 and the element on the line's origin) -- the rule itself is
+// evaluated.  The integer index is therefore always the rule's.
 __device__ inline Tap fast_tap(const DasArgs& a, int32_t b, float dtx, float A, float B, float r, float r2,
                                float rr) {
   const float q = A - r2 * B;
-  float X = q + rr;
-  X = (X > 0.0f) ? X : 0.0f;
+  const float X = q + rr;
   const float s = __builtin_amdgcn_sqrtf(X) + r;
   const float drx = q * __builtin_amdgcn_rcpf(s);
   const float c = a.K * dtx - a.T0;  // per pixel (hoisted out of element loops)
