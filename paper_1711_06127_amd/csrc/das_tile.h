@@ -638,9 +638,18 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
     bool slow = false;
     const ChunkHdr hd = *reinterpret_cast<const ChunkHdr*>(ct + SH::EC);
     float hyA = 1.0f, hyB = 1.0f;
-    if constexpr (MODE == 2 || MODE == 4) hyA = hann(hd.dyA, inv_w);
-    if constexpr (MODE == 2) hyB = hann(hd.dyB, inv_w);
-    T.scale = MODE == 4 ? hyA : 1.0f;
+    if constexpr (MODE == 2) {
+      hyA = hann(hd.dyA, inv_w);
+      hyB = hann(hd.dyB, inv_w);
+    }
+    if constexpr (MODE == 4) {
+      // consecutive chunks mostly lie on the same row: keep its factor
+      if (__any(hd.dyA != hy_dy)) {
+        hy = hann(hd.dyA, inv_w);
+        hy_dy = hd.dyA;
+      }
+    }
+    T.scale = MODE == 4 ? hy : 1.0f;
     float pden = 0.0f;  // the chunk's weights, before T.scale
 #pragma unroll
     for (int k = 0; k < SH::EC; ++k) {
