@@ -625,12 +625,12 @@ __device__ __forceinline__ void das_tile(const int16_t* __restrict__ rf, int fra
   // y offsets (the y factors computed once per chunk), 3 separable Hann in general (the y factor
   // kept while the offset repeats), 4 separable Hann whose chunk lies on one y offset (its y
   // factor is the chunk's common factor T.scale, applied to the chunk's sums and to its share
-  // of the weight total instead of to every weight).  An element is evaluated by the whole wave as soon as one
-  // lane has it inside its aperture (masking the others off would save no issue cycles); the
-  // lanes outside take weight zero.  Single-frame tiles keep the weight and the fraction of
-  // each tap (the sum interpolates, then weights); multi-frame tiles keep the two tap weights.
-  // T.slow is set in the lanes that have some tap inside the record but outside the staged
-  // window (slow_taps_uni finds which).
+  // of the weight total instead of to every weight).  An element is evaluated by the whole
+  // wave as soon as one lane has it inside its aperture (masking the others off would save no
+  // issue cycles); the lanes outside take weight zero.  Single-frame tiles keep the weight and
+  // the fraction of each tap (the sum interpolates, then weights); multi-frame tiles keep the
+  // two tap weights.  T.slow is set in the lanes that have some tap inside the record but
+  // outside the staged window (slow_taps_uni finds which).
   const uint64_t lane_mask = __builtin_amdgcn_ballot_w64(lane_ok);
   auto uni_taps = [&](auto mode_, const ChunkTap* ct, float& den) {
     constexpr int MODE = decltype(mode_)::value;

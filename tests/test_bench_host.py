@@ -47,6 +47,16 @@ def test_traffic_from_counter_collections(tmp_path, monkeypatch):
     assert bench.traffic_from_profile("das", 32) is None          # the kernel source changed
 
 
+def test_kernel_hash_ignores_comments_only():
+    a = 'int f(int x) { // the sum\n  return x + 1; /* one */ }\nconst char* s = "a // b";'
+    b = 'int f(int x) {\n\n  return x + 1;   }   const char* s = "a // b";'
+    c = 'int f(int x) { return x + 2; } const char* s = "a // b";'
+    d = 'int f(int x) { return x + 1; } const char* s = "a  b";'
+    assert bench.code_tokens(a) == bench.code_tokens(b)
+    assert bench.code_tokens(a) != bench.code_tokens(c)   # a changed constant
+    assert bench.code_tokens(a) != bench.code_tokens(d)   # a changed string literal
+
+
 def test_committed_traffic_matches_the_current_kernel():
     """profiles/traffic.json describes the delay-and-sum source as it is in the tree."""
     assert bench.traffic_from_profile("das", 32) is not None
