@@ -209,6 +209,39 @@ def test_beamform_unusual_grids(usbf, n_samples, depth_step, n_frames):
     assert rel_err(y, oracle.das(g, rf.cpu().numpy())) <= TOL
 
 
+@pytest.mark.parametrize("nx,ny,window,n_frames", [(2, 12, synth.HANN, 1), (5, 6, synth.HANN, 3),
+                                                   (8, 6, synth.RECT, 2)])
+def test_beamform_one_line_tiles_on_matrix_arrays(usbf, nx, ny, window, n_frames):
+    """Tiles of one line (one transmit per line) on matrix arrays whose rows are 2, 5 or 8
+    elements wide: element chunks that span three or more rows, chunks that lie on one row
+    (their Hann y factor applied to the chunk's sum), a rectangular window; a ragged last
+    depth tile; blocks of one and of several frames."""
+    g = synth.matrix_3d("rows", n_side=4, n_samples=600, n_lines_side=5, window=window)
+    g.el_pos = synth.geometry.matrix_array(nx, ny, 0.3e-3)
+    g.scan = None
+    assert usbf.lines_per_tx_hint(g.line_tx) == 1
+    rng = np.random.default_rng(100 * nx + ny)
+    rf = torch.as_tensor(rng.integers(-3000, 3000, size=(n_frames, g.n_tx, g.n_el, g.n_samples),
+                                      dtype=np.int16)).cuda()
+    y = usbf.beamform(rf, usbf.DeviceGeometry(g)).cpu().numpy()
+    assert rel_err(y, oracle.das(g, rf.cpu().numpy())) <= TOL
+
+
+@pytest.mark.parametrize("n_samples,depth_step,n_frames", [(301, 1, 3), (600, 3, 2), (2048, 16, 1)])
+def test_beamform_one_line_tiles_unusual_grids(usbf, n_samples, depth_step, n_frames):
+    """Tiles of one line with a record length that is not a multiple of 4, an odd depth step,
+    and a depth step so large that the staged windows are capped (the lanes with taps outside
+    them re-derive those taps and read global memory)."""
+    g = synth.linear_2d("odd1", n_el=16, n_tx=12, lines_per_tx=1, line_pitch=0.3e-3, n_samples=n_samples,
+                        depth_step=depth_step, scan_n=(16, 16))
+    assert usbf.lines_per_tx_hint(g.line_tx) == 1
+    rng = np.random.default_rng(n_samples + 7)
+    rf = torch.as_tensor(rng.integers(-30000, 30000, size=(n_frames, g.n_tx, g.n_el, g.n_samples),
+                                      dtype=np.int16)).cuda()
+    y = usbf.beamform(rf, usbf.DeviceGeometry(g)).cpu().numpy()
+    assert rel_err(y, oracle.das(g, rf.cpu().numpy())) <= TOL
+
+
 def test_beamform_deterministic(usbf):
     g = synth.config_small_2d()
     rf = sim(g, 1234)
